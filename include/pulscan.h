@@ -1,0 +1,199 @@
+/*
+ * pulscan.h -- C ABI of the MI355X (gfx950) boxcar filter-bank search.
+ *
+ * The search is the hot path of Pulscan (White et al. 2024): complex
+ * Fourier amplitudes are normalised block by block (median / MAD of the
+ * real and imaginary parts, section 2.2.3, with the median of medians of
+ * section 2.5 and the appendix algorithm "Median of Medians Normalisation"),
+ * squared into power (section 2.2.3), filtered by unit boxcars of every width
+ * 1..zmax (the recursion of section 2.2.5), reduced to per-chunk maxima for
+ * every width (appendix algorithm "Boxcar Filtering Process"), and the maxima
+ * whose Bonferroni-corrected Gaussian-equivalent significance reaches a
+ * threshold are returned as candidates (section 2.2.3).
+ *
+ * Conventions shared by every entry point:
+ *   - A width w covers bins [bin, bin + w); the paper's drift is z = w - 1
+ *     and a width-w boxcar of chi^2(2) powers is chi^2(2w).
+ *   - Windows exist only where they fit: bin + w <= nbins.
+ *   - Chunk c holds the window starts [c*chunk, min((c+1)*chunk, nbins)).
+ *     Each (chunk, width) yields at most one candidate: the largest boxcar
+ *     power of that width starting in the chunk, at the smallest such bin.
+ *   - The normalisation block defaults to the chunk.  The last, partial block
+ *     takes its statistics over the last `block` bins.  A block whose MAD is
+ *     0 normalises to 0.  The MAD scale is 1 / Phi^-1(3/4).
+ *   - ntrials (the Bonferroni factor) defaults to nbins * (number of
+ *     searched widths).
+ *   - Candidates come out in canonical order: ascending (spectrum, chunk,
+ *     width).  Results are deterministic.
+ *   - Inputs must be finite; NaN or infinite amplitudes give undefined
+ *     candidates (no crash).
+ *
+ * Memory: spectra, tables and on_device candidate buffers are DEVICE
+ * pointers owned by the caller, read-only for inputs and never retained
+ * after the call returns (or, for asynchronous calls, after the stream
+ * reaches the end of the call's work).  A context owns all scratch memory
+ * (thresholds, candidate staging, counters) and grows it on demand.
+ *
+ * Errors: every entry point returns a pulscan_status; nothing is thrown.  On
+ * any error other than PULSCAN_EOVERFLOW no output is written.
+ *
+ * Threads and streams: a context may be used by one host thread at a time,
+ * and its calls must not overlap on different streams.  The plain
+ * pulscan_search uses an internal default context, created on the device
+ * that is current at its first call.
+ */
+#ifndef PULSCAN_H
+#define PULSCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PULSCAN_OK = 0,
+  PULSCAN_EINVAL = -1,      /* invalid argument (null pointer, bad size, bad option)   */
+  PULSCAN_ENOMEM = -2,      /* device or host allocation failed                          */
+  PULSCAN_EOVERFLOW = -3,   /* more candidates than out->capacity (see pulscan_search)  */
+  PULSCAN_EHIP = -4,        /* a HIP runtime call failed                                 */
+  PULSCAN_EUNSUPPORTED = -5 /* valid for the method but outside what the kernels support */
+} pulscan_status;
+
+enum { PULSCAN_NORM_MOM = 0, PULSCAN_NORM_EXACT = 1 };
+enum { PULSCAN_W_ALL = 0, PULSCAN_W_LOG2 = 1 };
+
+/* One complex Fourier amplitude: interleaved real and imaginary parts, the
+ * layout of a complex FP32 FFT output (the paper's .fft input, section 2.2.2). */
+typedef struct {
+  float re, im;
+} pulscan_complex;
+
+/* One candidate: a per-chunk maximum whose significance reached the threshold. */
+typedef struct {
+  uint32_t spectrum; /* index in the batch; 0 for single-spectrum calls          */
+  uint32_t bin;      /* left edge of the window, 0-based (the paper's r-bin)     */
+  uint32_t width;    /* boxcar width 1..zmax; the paper's z-bin is width - 1     */
+  float power;       /* boxcar power of the window, FP32                         */
+  float sigma;       /* Bonferroni-corrected Gaussian-equivalent significance    */
+  uint32_t chunk;    /* chunk index, bin / chunk                                 */
+} pulscan_candidate; /* 24 bytes */
+
+/* Caller-owned candidate buffer. */
+typedef struct {
+  pulscan_candidate *data; /* capacity entries; host memory, or device if on_device */
+  uint64_t capacity;
+  uint64_t count;          /* out: the true number of candidates (may exceed capacity)
+                              -- set by synchronous calls                            */
+  int32_t on_device;       /* 1: data is a device pointer                             */
+  int32_t reserved;
+  uint64_t *count_device;  /* optional device pointer: receives the true count; the
+                              only count an asynchronous call delivers                */
+} pulscan_candidates;
+
+/* Options of the _ex and batched calls (fill with pulscan_opts_default). */
+typedef struct {
+  int32_t norm;         /* PULSCAN_NORM_MOM (default): median of medians; the GPU
+                           kernels support 4^k blocks of 64..4096 bins.
+                           PULSCAN_NORM_EXACT: exact median/MAD (not yet on GPU:
+                           PULSCAN_EUNSUPPORTED)                                   */
+  int32_t norm_block;   /* normalisation block in bins; 0 = chunk                    */
+  double ntrials;       /* Bonferroni trials; 0 = nbins * searched widths            */
+  int32_t width_search; /* PULSCAN_W_ALL (default): widths 1..zmax.
+                           PULSCAN_W_LOG2: only widths w with z = w - 1 a power of
+                           two (2, 3, 5, 9, 17, ...), section 4.1.3; every width
+                           is still summed, the others are just not searched        */
+  int32_t async;        /* 0 (default): wait for the stream and set out->count.
+                           1: enqueue only; needs out->on_device and
+                           out->count_device                                         */
+  void *stream;         /* hipStream_t to run on; NULL = the context's own stream   */
+} pulscan_opts;
+
+typedef struct pulscan_ctx pulscan_ctx;
+
+/* Human-readable name of a status code. */
+const char *pulscan_strerror(int status);
+
+/* Default options: MoM normalisation, block = chunk, default ntrials, all widths,
+ * synchronous, the context's stream. */
+void pulscan_opts_default(pulscan_opts *opts);
+
+/* Create a context on HIP device `device` (it becomes current for the calls
+ * of this thread that use the context).  Returns EINVAL for a null ctx or a
+ * bad device, EHIP if the runtime fails. */
+int pulscan_ctx_create(pulscan_ctx **ctx, int device);
+
+/* Release a context and all its device memory.  NULL is ignored. */
+void pulscan_ctx_destroy(pulscan_ctx *ctx);
+
+/* Search one spectrum (the four steps above) with default options on the
+ * default context, synchronously (thread-safe: calls are serialised).
+ *   spectrum      device pointer, nbins complex amplitudes
+ *   nbins         >= max(chunk, zmax) and < 2^32
+ *   zmax          largest boxcar width, >= 1
+ *   chunk         bins per chunk (and per normalisation block): a power of 4 in
+ *                 64..4096 with the default options
+ *   sigma_thresh  emit a (chunk, width) maximum when its corrected sigma >= this
+ *   out           candidates; out->count = true count.  If it exceeds
+ *                 out->capacity, the first capacity candidates (canonical order)
+ *                 are written and PULSCAN_EOVERFLOW is returned.            */
+int pulscan_search(const pulscan_complex *spectrum, size_t nbins, int zmax, int chunk,
+                   float sigma_thresh, pulscan_candidates *out);
+
+/* pulscan_search on an explicit context with options (opts NULL = defaults).
+ * chunk must be a multiple of 64 (at most 16384); see pulscan_opts for the
+ * normalisation block. */
+int pulscan_search_ex(pulscan_ctx *ctx, const pulscan_complex *spectrum, size_t nbins, int zmax,
+                      int chunk, float sigma_thresh, const pulscan_opts *opts,
+                      pulscan_candidates *out);
+
+/* Search nspec spectra of independent lengths and widths in one fused launch.
+ *   spectra, nbins, zmax   host arrays of nspec entries (spectra[s] on device)
+ *   chunk                  common chunk; 0 = chosen by the library from
+ *                          {256, 1024, 4096}, the choice returned in *chunk_used
+ *   opts.ntrials           applied per spectrum when non-zero; 0 = nbins[s] * widths
+ * Candidates of all spectra are returned together, ordered by spectrum.
+ * Validation is per spectrum as in pulscan_search_ex; one bad spectrum fails
+ * the call. */
+int pulscan_search_batched(pulscan_ctx *ctx, int nspec, const pulscan_complex *const *spectra,
+                           const uint64_t *nbins, const int32_t *zmax, int chunk,
+                           float sigma_thresh, const pulscan_opts *opts, pulscan_candidates *out,
+                           int *chunk_used);
+
+/* Dense per-chunk maxima for parity checks: the search without the threshold.
+ *   M, I    device, nchunks x zmax (row = chunk): the maximum boxcar power of each
+ *           (chunk, width) and its bin; -inf and 0xFFFFFFFF where no window fits
+ *   power   optional device output, nbins normalised powers (NULL to skip)
+ *   stats   optional device output, nblocks x 4: median_re, mad_re, median_im,
+ *           mad_im of each normalisation block (NULL to skip)
+ * Synchronous. */
+int pulscan_debug_tables(pulscan_ctx *ctx, const pulscan_complex *spectrum, size_t nbins,
+                         int zmax, int chunk, const pulscan_opts *opts, float *M, uint32_t *I,
+                         float *power, float *stats);
+
+/* The boxcar bank and per-chunk maxima alone, on a caller-supplied power
+ * array (device, nbins floats >= 0), skipping normalisation: integer-valued
+ * powers give exact sums.  M, I as in pulscan_debug_tables.  Synchronous. */
+int pulscan_debug_bank_from_power(pulscan_ctx *ctx, const float *power, size_t nbins, int zmax,
+                                  int chunk, float *M, uint32_t *I);
+
+/* The per-width power thresholds the search compares against: T_host[w-1] is
+ * the smallest FP32 power whose corrected sigma (width w, ntrials) reaches
+ * sigma_thresh, for w = 1..zmax (+inf for widths not searched under
+ * width_search).  Computed in FP64 on the device.  Synchronous. */
+int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, double ntrials,
+                            int width_search, float *T_host);
+
+/* Kernel timing: when enabled, every bank-kernel launch of the context is
+ * bracketed by HIP events on its stream.  pulscan_ctx_kernel_time waits for
+ * the recorded launches, returns their summed duration in milliseconds and
+ * their number, and clears the record. */
+int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable);
+int pulscan_ctx_kernel_time(pulscan_ctx *ctx, double *total_ms, uint64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PULSCAN_H */

@@ -84,7 +84,7 @@ def lib():
         L.oracle_power_for_sigma.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
         L.oracle_search.restype = i64
         L.oracle_search.argtypes = [fp, i64, ctypes.c_int, i64, ctypes.c_double, i64, ctypes.c_int,
-                                    ctypes.c_double, i64, ctypes.POINTER(_Cand), dp,
+                                    ctypes.c_double, ctypes.c_int, i64, ctypes.POINTER(_Cand), dp,
                                     ctypes.POINTER(ctypes.c_int64), dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -201,8 +201,13 @@ class SearchResult:
         self.P = P
 
 
+W_ALL = 0
+W_LOG2 = 1
+
+
 def search(spec, zmax: int, chunk: int, sigma: float, norm_block: int = 0, mode: int = NORM_MOM,
-           ntrials: float = 0.0, tables: bool = False, cap: int = None) -> SearchResult:
+           ntrials: float = 0.0, tables: bool = False, cap: int = None,
+           width_search: int = W_ALL) -> SearchResult:
     """Full search of one spectrum; candidates in (chunk, width) order."""
     s = _as_spec(spec)
     n = s.shape[0]
@@ -218,7 +223,7 @@ def search(spec, zmax: int, chunk: int, sigma: float, norm_block: int = 0, mode:
         P = np.empty(n)
         mp, ip, pp = _dptr(M), I.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(P)
     cnt = lib().oracle_search(s.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, zmax, chunk,
-                              sigma, norm_block, mode, ntrials, cap,
+                              sigma, norm_block, mode, ntrials, width_search, cap,
                               out.ctypes.data_as(ctypes.POINTER(_Cand)), mp, ip, pp)
     if cnt < 0:
         raise ValueError("oracle_search rejected its arguments")

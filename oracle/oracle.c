@@ -327,20 +327,35 @@ typedef struct {
   double logp;    /* corrected log p */
 } oracle_candidate;
 
+/* Widths searched for candidates (all are summed): every width (mode 0), or
+ * only those whose drift z = w - 1 is a power of two (mode 1, the
+ * logarithmic z sampling of section 4.1.3: z = 1, 2, 4, 8, ...). */
+static int width_is_searched(int w, int width_search) {
+  if (width_search == 1) {
+    int z = w - 1;
+    return z > 0 && (z & (z - 1)) == 0;
+  }
+  return 1;
+}
+
 /* Run steps 1-5 on one spectrum and emit, in (chunk, width) order, every
- * per-chunk maximum whose corrected significance reaches sigma_thresh.
- * Every width 1..zmax is searched; ntrials <= 0 means nbins * zmax.
+ * per-chunk maximum of a searched width whose corrected significance reaches
+ * sigma_thresh.  ntrials <= 0 means nbins * (number of searched widths).
  * Writes at most `cap` candidates to `out` and returns the total count, or
  * -1 on invalid arguments or allocation failure.  If M_out / I_out are
  * non-null they receive the full (nchunks x zmax) maxima tables and P_out
  * the normalised power. */
 int64_t oracle_search(const float *spec, int64_t n, int zmax, int64_t chunk, double sigma_thresh,
-                      int64_t norm_block, int mode, double ntrials, int64_t cap,
+                      int64_t norm_block, int mode, double ntrials, int width_search, int64_t cap,
                       oracle_candidate *out, double *M_out, int64_t *I_out, double *P_out) {
   if (!spec || n < 1 || zmax < 1 || chunk < 1) return -1;
   if (norm_block <= 0) norm_block = chunk;
   if (norm_block > n || zmax > n) return -1;
-  if (ntrials <= 0.0) ntrials = (double)n * zmax;
+  if (ntrials <= 0.0) {
+    int searched = 0;
+    for (int w = 1; w <= zmax; ++w) searched += width_is_searched(w, width_search);
+    ntrials = (double)n * (searched > 0 ? searched : 1);
+  }
   int64_t nchunks = (n + chunk - 1) / chunk;
   double *re = (double *)malloc((size_t)n * sizeof(double));
   double *im = (double *)malloc((size_t)n * sizeof(double));
@@ -361,7 +376,8 @@ int64_t oracle_search(const float *spec, int64_t n, int zmax, int64_t chunk, dou
   }
   count = 0;
   for (int64_t e = 0; e < nchunks * zmax; ++e) {
-    if (I[e] < 0 || !(lp[e] <= lthresh) || !(lp[e] < 0.0)) continue;
+    if (I[e] < 0 || !width_is_searched((int)(e % zmax) + 1, width_search)) continue;
+    if (!(lp[e] <= lthresh) || !(lp[e] < 0.0)) continue;
     if (count < cap && out) {
       oracle_candidate *o = &out[count];
       o->chunk = e / zmax;

@@ -1,0 +1,316 @@
+"""Python binding of the MI355X boxcar-search library (``libpulscan.so``).
+
+Argument marshalling only: every step of the search runs in the library's
+HIP kernels.  Device memory and streams come from PyTorch tensors and
+streams.  The names follow the C ABI declared in ``include/pulscan.h``.
+
+There is no fallback: if the library has not been built, importing the
+binding's functions raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libpulscan.so")
+
+PULSCAN_OK = 0
+PULSCAN_EINVAL = -1
+PULSCAN_ENOMEM = -2
+PULSCAN_EOVERFLOW = -3
+PULSCAN_EHIP = -4
+PULSCAN_EUNSUPPORTED = -5
+PULSCAN_NORM_MOM = 0
+PULSCAN_NORM_EXACT = 1
+PULSCAN_W_ALL = 0
+PULSCAN_W_LOG2 = 1
+
+
+class pulscan_candidate(ctypes.Structure):
+    _fields_ = [("spectrum", ctypes.c_uint32), ("bin", ctypes.c_uint32),
+                ("width", ctypes.c_uint32), ("power", ctypes.c_float),
+                ("sigma", ctypes.c_float), ("chunk", ctypes.c_uint32)]
+
+
+CANDIDATE_DTYPE = np.dtype([("spectrum", np.uint32), ("bin", np.uint32), ("width", np.uint32),
+                            ("power", np.float32), ("sigma", np.float32), ("chunk", np.uint32)])
+
+
+class pulscan_candidates(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("count", ctypes.c_uint64), ("on_device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("count_device", ctypes.c_void_p)]
+
+
+class pulscan_opts(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_int32), ("norm_block", ctypes.c_int32),
+                ("ntrials", ctypes.c_double), ("width_search", ctypes.c_int32),
+                ("async_", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(pulscan_candidate) == 24 == CANDIDATE_DTYPE.itemsize
+assert ctypes.sizeof(pulscan_candidates) == 40
+assert ctypes.sizeof(pulscan_opts) == 32
+
+# every function the header declares: name -> (restype, argtypes)
+_vp, _sz, _i, _f, _d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float, ctypes.c_double
+SIGNATURES = {
+    "pulscan_strerror": (ctypes.c_char_p, [_i]),
+    "pulscan_opts_default": (None, [ctypes.POINTER(pulscan_opts)]),
+    "pulscan_ctx_create": (_i, [ctypes.POINTER(_vp), _i]),
+    "pulscan_ctx_destroy": (None, [_vp]),
+    "pulscan_search": (_i, [_vp, _sz, _i, _i, _f, ctypes.POINTER(pulscan_candidates)]),
+    "pulscan_search_ex": (_i, [_vp, _vp, _sz, _i, _i, _f, ctypes.POINTER(pulscan_opts),
+                               ctypes.POINTER(pulscan_candidates)]),
+    "pulscan_search_batched": (_i, [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64),
+                                    ctypes.POINTER(ctypes.c_int32), _i, _f,
+                                    ctypes.POINTER(pulscan_opts),
+                                    ctypes.POINTER(pulscan_candidates), ctypes.POINTER(_i)]),
+    "pulscan_debug_tables": (_i, [_vp, _vp, _sz, _i, _i, ctypes.POINTER(pulscan_opts), _vp, _vp,
+                                  _vp, _vp]),
+    "pulscan_debug_bank_from_power": (_i, [_vp, _vp, _sz, _i, _i, _vp, _vp]),
+    "pulscan_threshold_table": (_i, [_vp, _i, _f, _d, _i, ctypes.POINTER(ctypes.c_float)]),
+    "pulscan_ctx_set_timing": (_i, [_vp, _i]),
+    "pulscan_ctx_kernel_time": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint64)]),
+}
+
+_lib = None
+
+
+class PulscanError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        msg = lib().pulscan_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg} ({status})" if where else f"{msg} ({status})")
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2406_15186_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str, allow_overflow: bool = False) -> int:
+    if status == PULSCAN_OK or (allow_overflow and status == PULSCAN_EOVERFLOW):
+        return status
+    raise PulscanError(status, where)
+
+
+def _spectrum_ptr(spectrum) -> tuple:
+    """(device pointer, nbins) of a complex64 (n,) or float32 (n, 2) CUDA tensor."""
+    import torch
+    if not isinstance(spectrum, torch.Tensor) or not spectrum.is_cuda:
+        raise TypeError("spectrum must be a CUDA (HIP) torch tensor")
+    if not spectrum.is_contiguous():
+        raise ValueError("spectrum must be contiguous")
+    if spectrum.dtype == torch.complex64:
+        n = spectrum.numel()
+    elif spectrum.dtype == torch.float32 and spectrum.dim() == 2 and spectrum.shape[1] == 2:
+        n = spectrum.shape[0]
+    else:
+        raise TypeError("spectrum must be complex64 (n,) or float32 (n, 2)")
+    return spectrum.data_ptr(), n
+
+
+def pulscan_opts_default() -> pulscan_opts:
+    o = pulscan_opts()
+    lib().pulscan_opts_default(ctypes.byref(o))
+    return o
+
+
+def make_opts(norm: int = PULSCAN_NORM_MOM, norm_block: int = 0, ntrials: float = 0.0,
+              width_search: int = PULSCAN_W_ALL, async_: bool = False, stream=None) -> pulscan_opts:
+    o = pulscan_opts_default()
+    o.norm, o.norm_block, o.ntrials = norm, norm_block, ntrials
+    o.width_search, o.async_ = width_search, int(bool(async_))
+    if stream is not None:
+        o.stream = stream if isinstance(stream, int) else stream.cuda_stream
+    return o
+
+
+class Context:
+    """A library context (``pulscan_ctx``) on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._ctx = ctypes.c_void_p()
+        _check(lib().pulscan_ctx_create(ctypes.byref(self._ctx), device), "pulscan_ctx_create")
+        self.device = device
+
+    def close(self):
+        if self._ctx:
+            lib().pulscan_ctx_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    # -- searches ---------------------------------------------------------
+    def pulscan_search_ex(self, spectrum, zmax: int, chunk: int, sigma_thresh: float,
+                          capacity: Optional[int] = None, opts: Optional[pulscan_opts] = None,
+                          out_device=None, count_device=None):
+        """Search one spectrum.  Returns (candidates, true_count).
+
+        Host output by default (a numpy structured array of CANDIDATE_DTYPE).
+        With ``out_device`` (a CUDA uint8 tensor of capacity*24 bytes) the
+        candidates stay on the device and the array returned is None.
+        """
+        ptr, n = _spectrum_ptr(spectrum)
+        if opts is None:
+            opts = pulscan_opts_default()
+        if capacity is None:
+            capacity = ((n + chunk - 1) // chunk) * zmax
+        out = pulscan_candidates()
+        host = None
+        if out_device is not None:
+            out.data = out_device.data_ptr()
+            out.on_device = 1
+        else:
+            host = np.zeros(max(capacity, 1), dtype=CANDIDATE_DTYPE)
+            out.data = host.ctypes.data
+        out.capacity = capacity
+        if count_device is not None:
+            out.count_device = count_device.data_ptr()
+        st = lib().pulscan_search_ex(self._ctx, ptr, n, zmax, chunk, sigma_thresh,
+                                     ctypes.byref(opts), ctypes.byref(out))
+        _check(st, "pulscan_search_ex", allow_overflow=True)
+        if host is None:
+            return None, int(out.count)
+        return host[:min(int(out.count), capacity)].copy(), int(out.count)
+
+    def pulscan_search_batched(self, spectra: Sequence, zmax: Sequence[int], chunk: int,
+                               sigma_thresh: float, capacity: Optional[int] = None,
+                               opts: Optional[pulscan_opts] = None, out_device=None,
+                               count_device=None):
+        """Search several spectra in one launch.  Returns (candidates, true_count, chunk_used)."""
+        ns = len(spectra)
+        ptrs = (ctypes.c_void_p * ns)()
+        ns_arr = (ctypes.c_uint64 * ns)()
+        zs = (ctypes.c_int32 * ns)()
+        cap_auto = 0
+        for i, (s, z) in enumerate(zip(spectra, zmax)):
+            p, n = _spectrum_ptr(s)
+            ptrs[i], ns_arr[i], zs[i] = p, n, int(z)
+            cap_auto += ((n + max(chunk, 64) - 1) // max(chunk, 64)) * int(z)
+        if opts is None:
+            opts = pulscan_opts_default()
+        if capacity is None:
+            capacity = cap_auto
+        out = pulscan_candidates()
+        host = None
+        if out_device is not None:
+            out.data = out_device.data_ptr()
+            out.on_device = 1
+        else:
+            host = np.zeros(max(capacity, 1), dtype=CANDIDATE_DTYPE)
+            out.data = host.ctypes.data
+        out.capacity = capacity
+        if count_device is not None:
+            out.count_device = count_device.data_ptr()
+        used = ctypes.c_int(0)
+        st = lib().pulscan_search_batched(self._ctx, ns, ptrs, ns_arr, zs, chunk, sigma_thresh,
+                                          ctypes.byref(opts), ctypes.byref(out), ctypes.byref(used))
+        _check(st, "pulscan_search_batched", allow_overflow=True)
+        if host is None:
+            return None, int(out.count), used.value
+        return host[:min(int(out.count), capacity)].copy(), int(out.count), used.value
+
+    # -- parity helpers ---------------------------------------------------
+    def pulscan_debug_tables(self, spectrum, zmax: int, chunk: int,
+                             opts: Optional[pulscan_opts] = None, want_power: bool = True,
+                             want_stats: bool = True):
+        """Dense per-chunk maxima (M, I), and optionally power and block stats, as CUDA tensors."""
+        import torch
+        ptr, n = _spectrum_ptr(spectrum)
+        if opts is None:
+            opts = pulscan_opts_default()
+        block = opts.norm_block if opts.norm_block > 0 else chunk
+        nc = (n + chunk - 1) // chunk
+        dev = spectrum.device
+        M = torch.empty((nc, zmax), dtype=torch.float32, device=dev)
+        I = torch.empty((nc, zmax), dtype=torch.int32, device=dev)
+        P = torch.empty(n, dtype=torch.float32, device=dev) if want_power else None
+        S = torch.empty(((n + block - 1) // block, 4), dtype=torch.float32, device=dev) \
+            if want_stats else None
+        torch.cuda.synchronize(dev)
+        st = lib().pulscan_debug_tables(self._ctx, ptr, n, zmax, chunk, ctypes.byref(opts),
+                                        M.data_ptr(), I.data_ptr(),
+                                        P.data_ptr() if P is not None else None,
+                                        S.data_ptr() if S is not None else None)
+        _check(st, "pulscan_debug_tables")
+        return M, I, P, S   # I holds uint32 bit patterns (0xFFFFFFFF: no window)
+
+    def pulscan_debug_bank_from_power(self, power, zmax: int, chunk: int):
+        """(M, I) of the bank run directly on a CUDA float32 power tensor."""
+        import torch
+        if power.dtype != torch.float32 or not power.is_cuda or not power.is_contiguous():
+            raise TypeError("power must be a contiguous CUDA float32 tensor")
+        n = power.numel()
+        nc = (n + chunk - 1) // chunk
+        M = torch.empty((nc, zmax), dtype=torch.float32, device=power.device)
+        I = torch.empty((nc, zmax), dtype=torch.int32, device=power.device)
+        torch.cuda.synchronize(power.device)
+        st = lib().pulscan_debug_bank_from_power(self._ctx, power.data_ptr(), n, zmax, chunk,
+                                                 M.data_ptr(), I.data_ptr())
+        _check(st, "pulscan_debug_bank_from_power")
+        return M, I
+
+    def pulscan_threshold_table(self, zmax: int, sigma_thresh: float, ntrials: float,
+                                width_search: int = PULSCAN_W_ALL) -> np.ndarray:
+        T = np.zeros(zmax, dtype=np.float32)
+        st = lib().pulscan_threshold_table(self._ctx, zmax, sigma_thresh, ntrials, width_search,
+                                           T.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        _check(st, "pulscan_threshold_table")
+        return T
+
+    # -- timing -----------------------------------------------------------
+    def pulscan_ctx_set_timing(self, enable: bool = True):
+        _check(lib().pulscan_ctx_set_timing(self._ctx, int(bool(enable))), "pulscan_ctx_set_timing")
+
+    def pulscan_ctx_kernel_time(self):
+        """(summed milliseconds, launches) of bank kernels since the last call."""
+        ms = ctypes.c_double(0.0)
+        k = ctypes.c_uint64(0)
+        _check(lib().pulscan_ctx_kernel_time(self._ctx, ctypes.byref(ms), ctypes.byref(k)),
+               "pulscan_ctx_kernel_time")
+        return ms.value, k.value
+
+
+def pulscan_search(spectrum, zmax: int, chunk: int, sigma_thresh: float,
+                   capacity: Optional[int] = None):
+    """The plain call on the library's default context: (candidates, true_count)."""
+    ptr, n = _spectrum_ptr(spectrum)
+    if capacity is None:
+        capacity = ((n + chunk - 1) // chunk) * zmax
+    host = np.zeros(max(capacity, 1), dtype=CANDIDATE_DTYPE)
+    out = pulscan_candidates()
+    out.data = host.ctypes.data
+    out.capacity = capacity
+    st = lib().pulscan_search(ptr, n, zmax, chunk, sigma_thresh, ctypes.byref(out))
+    _check(st, "pulscan_search", allow_overflow=True)
+    return host[:min(int(out.count), capacity)].copy(), int(out.count)
+
+
+def pulscan_strerror(status: int) -> str:
+    return lib().pulscan_strerror(status).decode()

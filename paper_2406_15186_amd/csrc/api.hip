@@ -1,0 +1,610 @@
+// C ABI of the boxcar search: argument checks, the context and its device
+// memory, threshold caching and the launch sequence
+//   thresholds (cached) -> fused bank kernel -> finalise (order + sigma).
+#include <float.h>
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace pulscan;
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct ThrKey {
+  bool valid = false;
+  uint32_t zmax = 0, zc = 0;
+  float sigma = 0.f;
+  double ntrials = 0.0;
+  int width_search = 0, debug = 0;
+  bool operator==(const ThrKey &o) const {
+    return valid && o.valid && zmax == o.zmax && zc == o.zc && sigma == o.sigma &&
+           ntrials == o.ntrials && width_search == o.width_search && debug == o.debug;
+  }
+};
+
+}  // namespace
+
+struct pulscan_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  DevBuf thr, stage, counts, total, outbuf, sort, descs, jobs;
+  size_t counts_per_parity = 0;
+  int parity = 0;
+  ThrKey thr_key;
+  // pinned staging of batched descriptors / threshold jobs
+  void *pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t pinned_ev = nullptr;
+  bool pinned_pending = false;
+  std::vector<SpecDesc> last_descs;  // what the device descriptor table holds
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
+};
+
+namespace {
+
+#define HIP_TRY(call)                       \
+  do {                                      \
+    if ((call) != hipSuccess) {             \
+      (void)hipGetLastError();              \
+      return PULSCAN_EHIP;                  \
+    }                                       \
+  } while (0)
+
+int grow(pulscan_ctx *ctx, DevBuf &b, size_t bytes, bool zero) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return PULSCAN_OK;
+  // a buffer may still be read by work queued earlier on the stream
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (b.p) {
+    HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return PULSCAN_ENOMEM;
+  }
+  b.bytes = want;
+  if (zero) {
+    HIP_TRY(hipMemset(b.p, 0, want));
+  }
+  return PULSCAN_OK;
+}
+
+int grow_pinned(pulscan_ctx *ctx, size_t bytes) {
+  if (ctx->pinned_pending) {
+    HIP_TRY(hipEventSynchronize(ctx->pinned_ev));
+    ctx->pinned_pending = false;
+  }
+  if (ctx->pinned_bytes >= bytes) return PULSCAN_OK;
+  if (ctx->pinned) {
+    HIP_TRY(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+  }
+  if (hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->pinned = nullptr;
+    return PULSCAN_ENOMEM;
+  }
+  ctx->pinned_bytes = bytes;
+  return PULSCAN_OK;
+}
+
+// Copy host bytes to device through the pinned staging buffer; the buffer is
+// reused only after the copy has completed (an event guards it).
+int upload(pulscan_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t stream) {
+  int st = grow_pinned(ctx, bytes);
+  if (st) return st;
+  memcpy(ctx->pinned, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst, ctx->pinned, bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(ctx->pinned_ev, stream));
+  ctx->pinned_pending = true;
+  return PULSCAN_OK;
+}
+
+bool is_pow4(uint64_t v) {
+  if (v == 0) return false;
+  while (v % 4 == 0) v /= 4;
+  return v == 1;
+}
+
+uint32_t searched_widths(uint32_t zmax, int ws) {
+  uint32_t c = 0;
+  for (uint32_t w = 1; w <= zmax; ++w) c += width_searched(w, ws) ? 1u : 0u;
+  return c;
+}
+
+// Checks shared by every search entry point.  Sets *block to the
+// normalisation block.
+int check_spectrum(const void *x, uint64_t n, int zmax, int chunk, const pulscan_opts &o,
+                   uint32_t *block) {
+  if (!x || zmax < 1 || chunk < 1 || n == 0 || n >= (1ull << 32)) return PULSCAN_EINVAL;
+  if (o.norm != PULSCAN_NORM_MOM && o.norm != PULSCAN_NORM_EXACT) return PULSCAN_EINVAL;
+  if (o.width_search != PULSCAN_W_ALL && o.width_search != PULSCAN_W_LOG2) return PULSCAN_EINVAL;
+  if (o.norm_block < 0) return PULSCAN_EINVAL;
+  if (!(o.ntrials == 0.0 || (isfinite(o.ntrials) && o.ntrials >= 1.0))) return PULSCAN_EINVAL;
+  const uint64_t B = o.norm_block > 0 ? (uint64_t)o.norm_block : (uint64_t)chunk;
+  if (n < B || n < (uint64_t)zmax) return PULSCAN_EINVAL;
+  if (o.norm == PULSCAN_NORM_MOM && !is_pow4(B)) return PULSCAN_EINVAL;
+  if (o.norm == PULSCAN_NORM_EXACT) return PULSCAN_EUNSUPPORTED;
+  if (B < 64 || B > 4096) return PULSCAN_EUNSUPPORTED;
+  if (chunk % 64 != 0 || chunk > kMaxTile) return PULSCAN_EUNSUPPORTED;
+  const uint64_t nchunks = (n + chunk - 1) / chunk;
+  if (nchunks * (uint64_t)zmax >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
+  *block = (uint32_t)B;
+  return PULSCAN_OK;
+}
+
+int check_out(const pulscan_candidates *out, bool async) {
+  if (!out) return PULSCAN_EINVAL;
+  if (out->capacity > 0 && !out->data) return PULSCAN_EINVAL;
+  if (async && (!out->on_device || !out->count_device)) return PULSCAN_EINVAL;
+  return PULSCAN_OK;
+}
+
+hipEvent_t take_event(pulscan_ctx *ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+struct SpecIn {
+  const void *x;
+  uint64_t n;
+  uint32_t zmax;
+};
+
+enum RunKind { kRunSearch, kRunTables, kRunFromPower };
+
+struct RunArgs {
+  RunKind kind = kRunSearch;
+  uint32_t chunk = 0, block = 0;
+  float sigma = 0.f;
+  pulscan_opts opts{};
+  pulscan_candidates *out = nullptr;
+  float *M = nullptr;
+  uint32_t *I = nullptr;
+  float *P_out = nullptr;
+  float *stats_out = nullptr;
+};
+
+int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t stream = a.opts.stream ? (hipStream_t)a.opts.stream : ctx->stream;
+  const int nspec = (int)specs.size();
+  const bool debug = a.kind != kRunSearch;
+  const int ws = debug ? PULSCAN_W_ALL : a.opts.width_search;
+
+  uint32_t zmax_max = 0;
+  for (const SpecIn &s : specs) zmax_max = s.zmax > zmax_max ? s.zmax : zmax_max;
+  Geometry g;
+  if (!choose_geometry(a.chunk, a.block, zmax_max, &g)) return PULSCAN_EUNSUPPORTED;
+
+  // descriptors
+  std::vector<SpecDesc> descs(nspec);
+  uint64_t tiles = 0, stage_total = 0, stage_max = 0;
+  uint32_t zc_max = 0;
+  for (int s = 0; s < nspec; ++s) {
+    SpecDesc &d = descs[s];
+    d.x = reinterpret_cast<const float2 *>(specs[s].x);
+    d.n = (uint32_t)specs[s].n;
+    d.zmax = specs[s].zmax;
+    d.zc = round_widths(d.zmax, g.K);
+    d.nchunks = (uint32_t)((specs[s].n + a.chunk - 1) / a.chunk);
+    d.tile_begin = tiles;
+    tiles += (specs[s].n + g.tile - 1) / g.tile;
+    d.stage_off = stage_total;
+    d.stage_cap = (uint64_t)d.nchunks * d.zmax;
+    stage_total += d.stage_cap;
+    stage_max = d.stage_cap > stage_max ? d.stage_cap : stage_max;
+    if (a.opts.ntrials > 0.0) {
+      d.ntrials = a.opts.ntrials;
+    } else {
+      const uint32_t sw = searched_widths(d.zmax, ws);
+      d.ntrials = (double)d.n * (double)(sw ? sw : 1u);
+    }
+    zc_max = d.zc > zc_max ? d.zc : zc_max;
+  }
+
+  // thresholds: table s at thr + s * zc_max
+  const void *thr_before = ctx->thr.p;
+  int st = grow(ctx, ctx->thr, (size_t)nspec * zc_max * sizeof(float), false);
+  if (st) return st;
+  if (ctx->thr.p != thr_before) ctx->thr_key.valid = false;
+  float *thr = static_cast<float *>(ctx->thr.p);
+  for (int s = 0; s < nspec; ++s) descs[s].thr = thr + (size_t)s * zc_max;
+  ThrKey key;
+  key.valid = nspec == 1;
+  key.zmax = descs[0].zmax;
+  key.zc = descs[0].zc;
+  key.sigma = a.sigma;
+  key.ntrials = descs[0].ntrials;
+  key.width_search = ws;
+  key.debug = debug ? 1 : 0;
+  if (!(nspec == 1 && key == ctx->thr_key)) {
+    std::vector<ThreshJob> jobs(nspec);
+    for (int s = 0; s < nspec; ++s)
+      jobs[s] = ThreshJob{const_cast<float *>(descs[s].thr), descs[s].zmax, descs[s].zc,
+                          descs[s].ntrials};
+    const ThreshJob *jobs_dev = nullptr;
+    if (nspec > 1) {
+      st = grow(ctx, ctx->jobs, jobs.size() * sizeof(ThreshJob), false);
+      if (st) return st;
+      st = upload(ctx, ctx->jobs.p, jobs.data(), jobs.size() * sizeof(ThreshJob), stream);
+      if (st) return st;
+      jobs_dev = static_cast<const ThreshJob *>(ctx->jobs.p);
+    }
+    HIP_TRY(launch_thresholds(jobs_dev, jobs[0], nspec, zc_max, (double)a.sigma, ws, key.debug,
+                              stream));
+    ctx->thr_key = key;
+  }
+
+  BankParams bp{};
+  bp.nspec = nspec;
+  bp.single = descs[0];
+  bp.total_tiles = tiles;
+  bp.chunk = a.chunk;
+  bp.block = a.block;
+  bp.tile = g.tile;
+  bp.zmax_max = zmax_max;
+  bp.nseg_lds = g.nseg_lds;
+  bp.mode = debug ? kModeTables : kModeSearch;
+  bp.from_power = a.kind == kRunFromPower ? 1 : 0;
+  bp.M = a.M;
+  bp.I = a.I;
+  bp.P_out = a.P_out;
+  bp.stats_out = a.stats_out;
+
+  // per-spectrum staging and counters (two parities: the finalise pass of
+  // one call clears the counters the next call will use)
+  unsigned long long *counts = nullptr, *counts_next = nullptr;
+  if (!debug) {
+    if (ctx->counts_per_parity < (size_t)nspec) {
+      st = grow(ctx, ctx->counts, 2 * (size_t)nspec * sizeof(unsigned long long), true);
+      if (st) return st;
+      ctx->counts_per_parity = ctx->counts.bytes / (2 * sizeof(unsigned long long));
+      ctx->parity = 0;
+    }
+    unsigned long long *cb = static_cast<unsigned long long *>(ctx->counts.p);
+    counts = cb + (size_t)ctx->parity * ctx->counts_per_parity;
+    counts_next = cb + (size_t)(1 - ctx->parity) * ctx->counts_per_parity;
+    st = grow(ctx, ctx->stage, stage_total * sizeof(StageEntry), false);
+    if (st) return st;
+    if (stage_max > (uint64_t)kSortLds) {
+      st = grow(ctx, ctx->sort, 2 * stage_total * sizeof(uint64_t), false);
+      if (st) return st;
+    }
+    st = grow(ctx, ctx->total, sizeof(unsigned long long), true);
+    if (st) return st;
+    bp.stage = static_cast<StageEntry *>(ctx->stage.p);
+    bp.stage_count = counts;
+  }
+
+  if (nspec > 1) {
+    const bool same = ctx->last_descs.size() == descs.size() &&
+                      memcmp(ctx->last_descs.data(), descs.data(), descs.size() * sizeof(SpecDesc)) == 0;
+    if (!same) {
+      st = grow(ctx, ctx->descs, descs.size() * sizeof(SpecDesc), false);
+      if (st) return st;
+      st = upload(ctx, ctx->descs.p, descs.data(), descs.size() * sizeof(SpecDesc), stream);
+      if (st) return st;
+      ctx->last_descs = descs;
+    }
+    bp.descs = static_cast<const SpecDesc *>(ctx->descs.p);
+  }
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    e0 = take_event(ctx);
+    e1 = take_event(ctx);
+    if (!e0 || !e1) return PULSCAN_EHIP;
+    HIP_TRY(hipEventRecord(e0, stream));
+  }
+  HIP_TRY(launch_bank(g, bp, tiles, stream));
+  if (ctx->timing) {
+    HIP_TRY(hipEventRecord(e1, stream));
+    ctx->ev_rec.emplace_back(e0, e1);
+  }
+
+  if (debug) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    return PULSCAN_OK;
+  }
+
+  // finalise into the caller's device buffer, or into ours for a host copy
+  pulscan_candidates *out = a.out;
+  pulscan_candidate *dst = out->data;
+  uint64_t cap = out->capacity;
+  if (!out->on_device) {
+    if (cap > stage_total) cap = stage_total;
+    st = grow(ctx, ctx->outbuf, (size_t)cap * sizeof(pulscan_candidate), false);
+    if (st) return st;
+    dst = static_cast<pulscan_candidate *>(ctx->outbuf.p);
+  }
+  FinalParams fp{};
+  fp.descs = nspec > 1 ? bp.descs : nullptr;
+  fp.nspec = nspec;
+  fp.stage = bp.stage;
+  fp.counts = counts;
+  fp.counts_next = counts_next;
+  fp.out = dst;
+  fp.capacity = cap;
+  fp.total = static_cast<unsigned long long *>(ctx->total.p);
+  fp.total2 = reinterpret_cast<unsigned long long *>(out->count_device);
+  fp.sort_scratch = static_cast<uint64_t *>(ctx->sort.p);
+  HIP_TRY(launch_finalise(fp, descs[0], stream));
+  ctx->parity ^= 1;
+
+  if (a.opts.async) return PULSCAN_OK;
+
+  unsigned long long total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, ctx->total.p, sizeof(total), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  out->count = total;
+  if (!out->on_device) {
+    const uint64_t ncopy = total < cap ? total : cap;
+    if (ncopy) {
+      HIP_TRY(hipMemcpyAsync(out->data, ctx->outbuf.p, ncopy * sizeof(pulscan_candidate),
+                             hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+    }
+  }
+  return total > out->capacity ? PULSCAN_EOVERFLOW : PULSCAN_OK;
+}
+
+std::mutex g_default_mu;
+pulscan_ctx *g_default = nullptr;
+
+}  // namespace
+
+extern "C" {
+
+const char *pulscan_strerror(int status) {
+  switch (status) {
+    case PULSCAN_OK: return "ok";
+    case PULSCAN_EINVAL: return "invalid argument";
+    case PULSCAN_ENOMEM: return "out of memory";
+    case PULSCAN_EOVERFLOW: return "more candidates than the output capacity";
+    case PULSCAN_EHIP: return "HIP runtime error";
+    case PULSCAN_EUNSUPPORTED: return "unsupported by the GPU kernels";
+    default: return "unknown status";
+  }
+}
+
+void pulscan_opts_default(pulscan_opts *o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->norm = PULSCAN_NORM_MOM;
+  o->width_search = PULSCAN_W_ALL;
+}
+
+int pulscan_ctx_create(pulscan_ctx **out, int device) {
+  if (!out) return PULSCAN_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return PULSCAN_EINVAL;
+  HIP_TRY(hipSetDevice(device));
+  pulscan_ctx *ctx = new (std::nothrow) pulscan_ctx();
+  if (!ctx) return PULSCAN_ENOMEM;
+  ctx->device = device;
+  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    pulscan_ctx_destroy(ctx);
+    return PULSCAN_EHIP;
+  }
+  *out = ctx;
+  return PULSCAN_OK;
+}
+
+void pulscan_ctx_destroy(pulscan_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  DevBuf *bufs[] = {&ctx->thr, &ctx->stage, &ctx->counts, &ctx->total,
+                    &ctx->outbuf, &ctx->sort, &ctx->descs, &ctx->jobs};
+  for (DevBuf *b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->pinned_ev) (void)hipEventDestroy(ctx->pinned_ev);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (auto &pr : ctx->ev_rec) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+int pulscan_search_ex(pulscan_ctx *ctx, const pulscan_complex *spectrum, size_t nbins, int zmax,
+                      int chunk, float sigma_thresh, const pulscan_opts *opts,
+                      pulscan_candidates *out) {
+  pulscan_opts o;
+  pulscan_opts_default(&o);
+  if (opts) o = *opts;
+  if (!ctx || !isfinite(sigma_thresh)) return PULSCAN_EINVAL;
+  int st = check_out(out, o.async != 0);
+  if (st) return st;
+  uint32_t block = 0;
+  st = check_spectrum(spectrum, nbins, zmax, chunk, o, &block);
+  if (st) return st;
+  RunArgs a;
+  a.kind = kRunSearch;
+  a.chunk = (uint32_t)chunk;
+  a.block = block;
+  a.sigma = sigma_thresh;
+  a.opts = o;
+  a.out = out;
+  std::vector<SpecIn> specs{SpecIn{spectrum, (uint64_t)nbins, (uint32_t)zmax}};
+  return run(ctx, specs, a);
+}
+
+int pulscan_search(const pulscan_complex *spectrum, size_t nbins, int zmax, int chunk,
+                   float sigma_thresh, pulscan_candidates *out) {
+  std::lock_guard<std::mutex> lock(g_default_mu);
+  if (!g_default) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int st = pulscan_ctx_create(&g_default, dev);
+    if (st) return st;
+  }
+  pulscan_opts o;
+  pulscan_opts_default(&o);
+  return pulscan_search_ex(g_default, spectrum, nbins, zmax, chunk, sigma_thresh, &o, out);
+}
+
+int pulscan_search_batched(pulscan_ctx *ctx, int nspec, const pulscan_complex *const *spectra,
+                           const uint64_t *nbins, const int32_t *zmax, int chunk,
+                           float sigma_thresh, const pulscan_opts *opts, pulscan_candidates *out,
+                           int *chunk_used) {
+  pulscan_opts o;
+  pulscan_opts_default(&o);
+  if (opts) o = *opts;
+  if (!ctx || nspec < 1 || !spectra || !nbins || !zmax || chunk < 0 || !isfinite(sigma_thresh))
+    return PULSCAN_EINVAL;
+  int st = check_out(out, o.async != 0);
+  if (st) return st;
+  const int c = chunk > 0 ? chunk : 1024;
+  uint32_t block = 0;
+  std::vector<SpecIn> specs(nspec);
+  for (int s = 0; s < nspec; ++s) {
+    uint32_t b = 0;
+    st = check_spectrum(spectra[s], nbins[s], zmax[s], c, o, &b);
+    if (st) return st;
+    block = b;
+    specs[s] = SpecIn{spectra[s], nbins[s], (uint32_t)zmax[s]};
+  }
+  if (chunk_used) *chunk_used = c;
+  RunArgs a;
+  a.kind = kRunSearch;
+  a.chunk = (uint32_t)c;
+  a.block = block;
+  a.sigma = sigma_thresh;
+  a.opts = o;
+  a.out = out;
+  return run(ctx, specs, a);
+}
+
+int pulscan_debug_tables(pulscan_ctx *ctx, const pulscan_complex *spectrum, size_t nbins,
+                         int zmax, int chunk, const pulscan_opts *opts, float *M, uint32_t *I,
+                         float *power, float *stats) {
+  pulscan_opts o;
+  pulscan_opts_default(&o);
+  if (opts) o = *opts;
+  o.async = 0;
+  if (!ctx || !M || !I) return PULSCAN_EINVAL;
+  uint32_t block = 0;
+  int st = check_spectrum(spectrum, nbins, zmax, chunk, o, &block);
+  if (st) return st;
+  RunArgs a;
+  a.kind = kRunTables;
+  a.chunk = (uint32_t)chunk;
+  a.block = block;
+  a.opts = o;
+  a.M = M;
+  a.I = I;
+  a.P_out = power;
+  a.stats_out = stats;
+  std::vector<SpecIn> specs{SpecIn{spectrum, (uint64_t)nbins, (uint32_t)zmax}};
+  return run(ctx, specs, a);
+}
+
+int pulscan_debug_bank_from_power(pulscan_ctx *ctx, const float *power, size_t nbins, int zmax,
+                                  int chunk, float *M, uint32_t *I) {
+  if (!ctx || !power || !M || !I || zmax < 1 || chunk < 1 || nbins == 0 ||
+      nbins >= (1ull << 32) || nbins < (size_t)zmax)
+    return PULSCAN_EINVAL;
+  if (chunk % 64 != 0 || chunk > kMaxTile) return PULSCAN_EUNSUPPORTED;
+  const uint64_t nchunks = (nbins + chunk - 1) / chunk;
+  if (nchunks * (uint64_t)zmax >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
+  RunArgs a;
+  a.kind = kRunFromPower;
+  a.chunk = (uint32_t)chunk;
+  a.block = 64;
+  pulscan_opts_default(&a.opts);
+  a.M = M;
+  a.I = I;
+  std::vector<SpecIn> specs{SpecIn{power, (uint64_t)nbins, (uint32_t)zmax}};
+  return run(ctx, specs, a);
+}
+
+int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, double ntrials,
+                            int width_search, float *T_host) {
+  if (!ctx || zmax < 1 || !T_host || !isfinite(sigma_thresh) || !isfinite(ntrials) ||
+      ntrials < 1.0)
+    return PULSCAN_EINVAL;
+  if (width_search != PULSCAN_W_ALL && width_search != PULSCAN_W_LOG2) return PULSCAN_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  DevBuf tmp;
+  if (hipMalloc(&tmp.p, (size_t)zmax * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return PULSCAN_ENOMEM;
+  }
+  ThreshJob job{static_cast<float *>(tmp.p), (uint32_t)zmax, (uint32_t)zmax, ntrials};
+  int st = PULSCAN_OK;
+  if (launch_thresholds(nullptr, job, 1, (uint32_t)zmax, (double)sigma_thresh, width_search, 0,
+                        ctx->stream) != hipSuccess ||
+      hipMemcpyAsync(T_host, tmp.p, (size_t)zmax * sizeof(float), hipMemcpyDeviceToHost,
+                     ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    st = PULSCAN_EHIP;
+  }
+  (void)hipFree(tmp.p);
+  return st;
+}
+
+int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable) {
+  if (!ctx) return PULSCAN_EINVAL;
+  ctx->timing = enable != 0;
+  return PULSCAN_OK;
+}
+
+int pulscan_ctx_kernel_time(pulscan_ctx *ctx, double *total_ms, uint64_t *launches) {
+  if (!ctx || !total_ms || !launches) return PULSCAN_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  double sum = 0.0;
+  int st = PULSCAN_OK;
+  for (auto &pr : ctx->ev_rec) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) != hipSuccess ||
+        hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) {
+      (void)hipGetLastError();
+      st = PULSCAN_EHIP;
+    }
+    sum += ms;
+    ctx->ev_pool.push_back(pr.first);
+    ctx->ev_pool.push_back(pr.second);
+  }
+  *launches = ctx->ev_rec.size();
+  *total_ms = sum;
+  ctx->ev_rec.clear();
+  return st;
+}
+
+}  // extern "C"

@@ -353,3 +353,25 @@ def test_emission_rule_matches_scipy(oracle_lib):
         ref = stats.norm.isf(min(stats.chi2.sf(cand["power"], 2 * cand["width"]) * nt, 1.0))
         assert cand["sigma"] == pytest.approx(ref, abs=1e-6)
     assert len(r.cands) > 0
+
+
+def test_log_width_sampling(oracle_lib):
+    """Section 4.1.3: only z = w - 1 in {1, 2, 4, 8, ...} is searched, and the
+    Bonferroni factor counts only those widths."""
+    import synth
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    Z = wl.zmax
+    full = oracle_lib.search(x, Z, wl.chunk, wl.sigma, tables=True)
+    logz = oracle_lib.search(x, Z, wl.chunk, wl.sigma, width_search=oracle_lib.W_LOG2)
+    searched = [w for w in range(1, Z + 1) if (w - 1) > 0 and ((w - 1) & (w - 2)) == 0]
+    assert searched == [2, 3, 5, 9, 17, 33]
+    assert set(logz.cands["width"].tolist()) <= set(searched)
+    nt = float(wl.nbins * len(searched))
+    expect = []
+    for c in range(full.M.shape[0]):
+        for w in searched:
+            if stats.norm.isf(min(stats.chi2.sf(full.M[c, w - 1], 2 * w) * nt, 1.0)) >= 6.0:
+                expect.append((c, w))
+    assert [(int(a), int(b)) for a, b in zip(logz.cands["chunk"], logz.cands["width"])] == expect
+    assert len(expect) > 0
