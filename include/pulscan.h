@@ -38,7 +38,9 @@
  * any error other than PULSCAN_EOVERFLOW no output is written.
  *
  * Threads and streams: a context may be used by one host thread at a time,
- * and its calls must not overlap on different streams.  The plain
+ * and its calls must not overlap on different streams.  Calls run on the
+ * stream given in the options (the null stream by default) and are ordered
+ * after work already queued there.  The plain
  * pulscan_search uses an internal default context, created on the device
  * that is current at its first call.
  */
@@ -107,7 +109,7 @@ typedef struct {
   int32_t async;        /* 0 (default): wait for the stream and set out->count.
                            1: enqueue only; needs out->on_device and
                            out->count_device                                         */
-  void *stream;         /* hipStream_t to run on; NULL = the context's own stream   */
+  void *stream;         /* hipStream_t to run on; NULL = the null (default) stream */
 } pulscan_opts;
 
 typedef struct pulscan_ctx pulscan_ctx;
@@ -116,7 +118,7 @@ typedef struct pulscan_ctx pulscan_ctx;
 const char *pulscan_strerror(int status);
 
 /* Default options: MoM normalisation, block = chunk, default ntrials, all widths,
- * synchronous, the context's stream. */
+ * synchronous, the null stream. */
 void pulscan_opts_default(pulscan_opts *opts);
 
 /* Create a context on HIP device `device` (it becomes current for the calls

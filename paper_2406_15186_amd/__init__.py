@@ -90,12 +90,18 @@ class PulscanError(RuntimeError):
 
 
 def lib() -> ctypes.CDLL:
-    """The loaded library.  Raises if it has not been built."""
+    """The loaded library.  Raises if it has not been built.
+
+    torch is imported first: the library then binds to the HIP runtime torch
+    has already loaded, so the process holds a single runtime and device
+    pointers and streams from torch are valid in the library's calls.
+    """
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2406_15186_amd.build` (hipcc, gfx950)")
+        import torch  # noqa: F401  (load torch's HIP runtime before ours binds)
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -180,7 +186,7 @@ class Context:
         if opts is None:
             opts = pulscan_opts_default()
         if capacity is None:
-            capacity = ((n + chunk - 1) // chunk) * zmax
+            capacity = ((n + chunk - 1) // chunk) * zmax if chunk > 0 and zmax > 0 else 0
         out = pulscan_candidates()
         host = None
         if out_device is not None:
@@ -212,7 +218,7 @@ class Context:
         for i, (s, z) in enumerate(zip(spectra, zmax)):
             p, n = _spectrum_ptr(s)
             ptrs[i], ns_arr[i], zs[i] = p, n, int(z)
-            cap_auto += ((n + max(chunk, 64) - 1) // max(chunk, 64)) * int(z)
+            cap_auto += ((n + max(chunk, 64) - 1) // max(chunk, 64)) * max(int(z), 0)
         if opts is None:
             opts = pulscan_opts_default()
         if capacity is None:
@@ -302,7 +308,7 @@ def pulscan_search(spectrum, zmax: int, chunk: int, sigma_thresh: float,
     """The plain call on the library's default context: (candidates, true_count)."""
     ptr, n = _spectrum_ptr(spectrum)
     if capacity is None:
-        capacity = ((n + chunk - 1) // chunk) * zmax
+        capacity = ((n + chunk - 1) // chunk) * zmax if chunk > 0 and zmax > 0 else 0
     host = np.zeros(max(capacity, 1), dtype=CANDIDATE_DTYPE)
     out = pulscan_candidates()
     out.data = host.ctypes.data

@@ -1,6 +1,7 @@
 // C ABI of the boxcar search: argument checks, the context and its device
 // memory, threshold caching and the launch sequence
-//   thresholds (cached) -> fused bank kernel -> finalise (order + sigma).
+//   thresholds (cached) -> fused bank kernel -> scan of tile counts -> emit
+//   (canonical order + FP64 sigma).
 #include <float.h>
 #include <math.h>
 #include <string.h>
@@ -36,10 +37,7 @@ struct ThrKey {
 
 struct pulscan_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
-  DevBuf thr, stage, counts, total, outbuf, sort, descs, jobs;
-  size_t counts_per_parity = 0;
-  int parity = 0;
+  DevBuf thr, pool, tile_count, tile_pos, tile_prefix, counters, outbuf, descs, jobs;
   ThrKey thr_key;
   // pinned staging of batched descriptors / threshold jobs
   void *pinned = nullptr;
@@ -55,6 +53,14 @@ struct pulscan_ctx {
 
 namespace {
 
+// Device-resident counters of a search; zeroed when allocated, the pool head
+// is reset by the scan kernel at the end of every search.
+struct Counters {
+  unsigned long long total;
+  uint32_t overflow;
+  uint32_t head;
+};
+
 #define HIP_TRY(call)                       \
   do {                                      \
     if ((call) != hipSuccess) {             \
@@ -66,8 +72,9 @@ namespace {
 int grow(pulscan_ctx *ctx, DevBuf &b, size_t bytes, bool zero) {
   if (bytes == 0) bytes = 8;
   if (b.bytes >= bytes) return PULSCAN_OK;
-  // a buffer may still be read by work queued earlier on the stream
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  // a buffer may still be read by work queued earlier on any stream
+  (void)ctx;
+  HIP_TRY(hipDeviceSynchronize());
   if (b.p) {
     HIP_TRY(hipFree(b.p));
     b.p = nullptr;
@@ -194,7 +201,7 @@ struct RunArgs {
 
 int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   HIP_TRY(hipSetDevice(ctx->device));
-  hipStream_t stream = a.opts.stream ? (hipStream_t)a.opts.stream : ctx->stream;
+  hipStream_t stream = (hipStream_t)a.opts.stream;
   const int nspec = (int)specs.size();
   const bool debug = a.kind != kRunSearch;
   const int ws = debug ? PULSCAN_W_ALL : a.opts.width_search;
@@ -206,7 +213,7 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
 
   // descriptors
   std::vector<SpecDesc> descs(nspec);
-  uint64_t tiles = 0, stage_total = 0, stage_max = 0;
+  uint64_t tiles = 0;
   uint32_t zc_max = 0;
   for (int s = 0; s < nspec; ++s) {
     SpecDesc &d = descs[s];
@@ -217,10 +224,6 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
     d.nchunks = (uint32_t)((specs[s].n + a.chunk - 1) / a.chunk);
     d.tile_begin = tiles;
     tiles += (specs[s].n + g.tile - 1) / g.tile;
-    d.stage_off = stage_total;
-    d.stage_cap = (uint64_t)d.nchunks * d.zmax;
-    stage_total += d.stage_cap;
-    stage_max = d.stage_cap > stage_max ? d.stage_cap : stage_max;
     if (a.opts.ntrials > 0.0) {
       d.ntrials = a.opts.ntrials;
     } else {
@@ -272,6 +275,7 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   bp.tile = g.tile;
   bp.zmax_max = zmax_max;
   bp.nseg_lds = g.nseg_lds;
+  bp.zc_max_pad = g.zc_max_pad;
   bp.mode = debug ? kModeTables : kModeSearch;
   bp.from_power = a.kind == kRunFromPower ? 1 : 0;
   bp.M = a.M;
@@ -279,29 +283,29 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   bp.P_out = a.P_out;
   bp.stats_out = a.stats_out;
 
-  // per-spectrum staging and counters (two parities: the finalise pass of
-  // one call clears the counters the next call will use)
-  unsigned long long *counts = nullptr, *counts_next = nullptr;
+  // staging: a pool for the candidates and per-tile counts and offsets
+  uint64_t worst = 0;
+  for (const SpecDesc &d : descs) worst += (uint64_t)d.nchunks * d.zmax;
+  if (worst >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
+  const uint32_t pool_cap = (uint32_t)(worst < (uint64_t)kPoolMax ? (worst ? worst : 1) : kPoolMax);
+  Counters *cnt = nullptr;
   if (!debug) {
-    if (ctx->counts_per_parity < (size_t)nspec) {
-      st = grow(ctx, ctx->counts, 2 * (size_t)nspec * sizeof(unsigned long long), true);
-      if (st) return st;
-      ctx->counts_per_parity = ctx->counts.bytes / (2 * sizeof(unsigned long long));
-      ctx->parity = 0;
-    }
-    unsigned long long *cb = static_cast<unsigned long long *>(ctx->counts.p);
-    counts = cb + (size_t)ctx->parity * ctx->counts_per_parity;
-    counts_next = cb + (size_t)(1 - ctx->parity) * ctx->counts_per_parity;
-    st = grow(ctx, ctx->stage, stage_total * sizeof(StageEntry), false);
+    st = grow(ctx, ctx->pool, (size_t)pool_cap * sizeof(StageEntry), false);
     if (st) return st;
-    if (stage_max > (uint64_t)kSortLds) {
-      st = grow(ctx, ctx->sort, 2 * stage_total * sizeof(uint64_t), false);
-      if (st) return st;
-    }
-    st = grow(ctx, ctx->total, sizeof(unsigned long long), true);
+    st = grow(ctx, ctx->tile_count, tiles * sizeof(uint32_t), false);
     if (st) return st;
-    bp.stage = static_cast<StageEntry *>(ctx->stage.p);
-    bp.stage_count = counts;
+    st = grow(ctx, ctx->tile_pos, tiles * sizeof(uint32_t), false);
+    if (st) return st;
+    st = grow(ctx, ctx->tile_prefix, (tiles + 1) * sizeof(uint32_t), false);
+    if (st) return st;
+    st = grow(ctx, ctx->counters, sizeof(Counters), true);
+    if (st) return st;
+    cnt = static_cast<Counters *>(ctx->counters.p);
+    bp.pool = static_cast<StageEntry *>(ctx->pool.p);
+    bp.pool_cap = pool_cap;
+    bp.pool_head = &cnt->head;
+    bp.tile_count = static_cast<uint32_t *>(ctx->tile_count.p);
+    bp.tile_pos = static_cast<uint32_t *>(ctx->tile_pos.p);
   }
 
   if (nspec > 1) {
@@ -335,36 +339,48 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
     return PULSCAN_OK;
   }
 
-  // finalise into the caller's device buffer, or into ours for a host copy
+  // emit into the caller's device buffer, or into ours for a host copy
   pulscan_candidates *out = a.out;
   pulscan_candidate *dst = out->data;
   uint64_t cap = out->capacity;
   if (!out->on_device) {
-    if (cap > stage_total) cap = stage_total;
+    if (cap > worst) cap = worst;
     st = grow(ctx, ctx->outbuf, (size_t)cap * sizeof(pulscan_candidate), false);
     if (st) return st;
     dst = static_cast<pulscan_candidate *>(ctx->outbuf.p);
   }
-  FinalParams fp{};
-  fp.descs = nspec > 1 ? bp.descs : nullptr;
-  fp.nspec = nspec;
-  fp.stage = bp.stage;
-  fp.counts = counts;
-  fp.counts_next = counts_next;
-  fp.out = dst;
-  fp.capacity = cap;
-  fp.total = static_cast<unsigned long long *>(ctx->total.p);
-  fp.total2 = reinterpret_cast<unsigned long long *>(out->count_device);
-  fp.sort_scratch = static_cast<uint64_t *>(ctx->sort.p);
-  HIP_TRY(launch_finalise(fp, descs[0], stream));
-  ctx->parity ^= 1;
+  ScanParams sp{};
+  sp.tile_count = bp.tile_count;
+  sp.tile_prefix = static_cast<uint32_t *>(ctx->tile_prefix.p);
+  sp.total_tiles = tiles;
+  sp.pool_head = &cnt->head;
+  sp.pool_cap = pool_cap;
+  sp.total = &cnt->total;
+  sp.total2 = reinterpret_cast<unsigned long long *>(out->count_device);
+  sp.overflow = &cnt->overflow;
+  HIP_TRY(launch_scan(sp, stream));
+  EmitParams ep{};
+  ep.descs = nspec > 1 ? bp.descs : nullptr;
+  ep.nspec = nspec;
+  ep.pool = bp.pool;
+  ep.pool_cap = pool_cap;
+  ep.tile_prefix = sp.tile_prefix;
+  ep.tile_pos = bp.tile_pos;
+  ep.total_tiles = tiles;
+  ep.out = dst;
+  ep.capacity = cap;
+  const uint64_t work = cap < worst ? cap : worst;
+  const uint32_t egrid = (uint32_t)(work / 256 + 1 < 512 ? work / 256 + 1 : 512);
+  HIP_TRY(launch_emit(ep, descs[0], egrid, stream));
 
   if (a.opts.async) return PULSCAN_OK;
 
-  unsigned long long total = 0;
-  HIP_TRY(hipMemcpyAsync(&total, ctx->total.p, sizeof(total), hipMemcpyDeviceToHost, stream));
+  Counters hc{};
+  HIP_TRY(hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
+  const unsigned long long total = hc.total;
   out->count = total;
+  if (hc.overflow) return PULSCAN_ENOMEM;
   if (!out->on_device) {
     const uint64_t ncopy = total < cap ? total : cap;
     if (ncopy) {
@@ -412,8 +428,7 @@ int pulscan_ctx_create(pulscan_ctx **out, int device) {
   pulscan_ctx *ctx = new (std::nothrow) pulscan_ctx();
   if (!ctx) return PULSCAN_ENOMEM;
   ctx->device = device;
-  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     pulscan_ctx_destroy(ctx);
     return PULSCAN_EHIP;
@@ -425,9 +440,10 @@ int pulscan_ctx_create(pulscan_ctx **out, int device) {
 void pulscan_ctx_destroy(pulscan_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf *bufs[] = {&ctx->thr, &ctx->stage, &ctx->counts, &ctx->total,
-                    &ctx->outbuf, &ctx->sort, &ctx->descs, &ctx->jobs};
+  (void)hipDeviceSynchronize();
+  DevBuf *bufs[] = {&ctx->thr,         &ctx->pool,     &ctx->tile_count, &ctx->tile_pos,
+                    &ctx->tile_prefix, &ctx->counters, &ctx->outbuf,     &ctx->descs,
+                    &ctx->jobs};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -437,7 +453,6 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
   }
-  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -568,10 +583,9 @@ int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, doub
   ThreshJob job{static_cast<float *>(tmp.p), (uint32_t)zmax, (uint32_t)zmax, ntrials};
   int st = PULSCAN_OK;
   if (launch_thresholds(nullptr, job, 1, (uint32_t)zmax, (double)sigma_thresh, width_search, 0,
-                        ctx->stream) != hipSuccess ||
-      hipMemcpyAsync(T_host, tmp.p, (size_t)zmax * sizeof(float), hipMemcpyDeviceToHost,
-                     ctx->stream) != hipSuccess ||
-      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                        nullptr) != hipSuccess ||
+      hipMemcpy(T_host, tmp.p, (size_t)zmax * sizeof(float), hipMemcpyDeviceToHost) !=
+          hipSuccess) {
     (void)hipGetLastError();
     st = PULSCAN_EHIP;
   }
@@ -582,6 +596,15 @@ int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, doub
 int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable) {
   if (!ctx) return PULSCAN_EINVAL;
   ctx->timing = enable != 0;
+  if (ctx->timing) {
+    // create the events up front so that timed calls do not create any
+    HIP_TRY(hipSetDevice(ctx->device));
+    while (ctx->ev_pool.size() < 2048) {
+      hipEvent_t e = nullptr;
+      HIP_TRY(hipEventCreate(&e));
+      ctx->ev_pool.push_back(e);
+    }
+  }
   return PULSCAN_OK;
 }
 

@@ -157,7 +157,7 @@ __device__ __forceinline__ void normalise_block(const float2 *__restrict__ x, ui
 // slots (zmax entries); bin0 is the spectrum bin of the lane's first start.
 template <int K>
 __device__ __forceinline__ void bank_segment(const float *__restrict__ Pl, uint32_t g,
-                                             uint32_t lane, const float *__restrict__ thr,
+                                             uint32_t lane, const float *__restrict__ Tl,
                                              uint32_t zmax, uint32_t zc,
                                              unsigned long long *slot_row, uint32_t bin0) {
   float s[K], q[2 * K];
@@ -176,12 +176,15 @@ __device__ __forceinline__ void bank_segment(const float *__restrict__ Pl, uint3
 #pragma unroll
       for (int v = 0; v < K; ++v) q[K + v] = bp[v * kRowPitch];
     }
+    float Tv[K];  // this block's thresholds (same LDS word for every lane)
+#pragma unroll
+    for (int u = 0; u < K; ++u) Tv[u] = Tl[wb + u];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
 #pragma unroll
       for (int k = 0; k < K; ++k) s[k] += q[k + u];  // width wb+u+1
       const float m = max_of<K>(s);
-      const float Tw = thr[wb + u];
+      const float Tw = Tv[u];
       if (m >= Tw) {
         const uint32_t w = wb + u + 1;
         if (w <= zmax) {
@@ -202,13 +205,17 @@ __device__ __forceinline__ void bank_segment(const float *__restrict__ Pl, uint3
 template <int K, int EPL>
 __global__ __launch_bounds__(kThreads) void bank_kernel(BankParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ uint32_t wave_sum[kWaves];
+  __shared__ uint32_t tile_base;
   constexpr uint32_t SEG = 64 * K;
   constexpr uint32_t B = 64 * EPL;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t T = p.tile, C = p.chunk;
   const uint32_t chunks_per_tile = T / C;
+  // LDS: slots (chunks_per_tile x zmax_max, 64-bit) | thresholds (zc_max) | power tile
   unsigned long long *slots = reinterpret_cast<unsigned long long *>(lds_raw);
-  float *Pl = reinterpret_cast<float *>(slots + (size_t)chunks_per_tile * p.zmax_max);
+  float *Tl = reinterpret_cast<float *>(slots + (size_t)chunks_per_tile * p.zmax_max);
+  float *Pl = Tl + p.zc_max_pad;
   const uint32_t plen = p.nseg_lds * K * kRowPitch;
 
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
@@ -237,6 +244,7 @@ __global__ __launch_bounds__(kThreads) void bank_kernel(BankParams p) {
     const uint32_t need = min(T + zmax - 1, rem);
 
     for (uint32_t i = threadIdx.x; i < chunks_per_tile * zmax; i += kThreads) slots[i] = 0ull;
+    for (uint32_t i = threadIdx.x; i < d.zc; i += kThreads) Tl[i] = d.thr[i];
     for (uint32_t i = threadIdx.x; i < plen; i += kThreads) Pl[i] = -INFINITY;
     __syncthreads();
 
@@ -257,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void bank_kernel(BankParams p) {
       const uint32_t seg0 = g * SEG;
       if (seg0 >= rem) break;
       const uint32_t c_local = seg0 / C;
-      bank_segment<K>(Pl, g, lane, d.thr, zmax, d.zc, slots + (size_t)c_local * zmax,
+      bank_segment<K>(Pl, g, lane, Tl, zmax, d.zc, slots + (size_t)c_local * zmax,
                       t0 + seg0 + lane * K);
     }
     __syncthreads();
@@ -266,27 +274,49 @@ __global__ __launch_bounds__(kThreads) void bank_kernel(BankParams p) {
     const uint32_t nch = min(chunks_per_tile, d.nchunks - chunk0);
     const uint32_t nsl = nch * zmax;
     if (p.mode == kModeSearch) {
-      for (uint32_t base = 0; base < nsl; base += kThreads) {
-        const uint32_t i = base + threadIdx.x;
+      // Stage the tile's maxima in slot order, i.e. (chunk, width) order:
+      // count, reserve one run of the pool, then write with ordered ranks.
+      uint32_t mine = 0;
+      for (uint32_t i = threadIdx.x; i < nsl; i += kThreads) mine += slots[i] != 0ull ? 1u : 0u;
+      for (int o = 32; o >= 1; o >>= 1) mine += __shfl_xor(mine, o, 64);
+      if (lane == 0) wave_sum[wave] = mine;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int v = 0; v < kWaves; ++v) tot += wave_sum[v];
+        const uint32_t base = tot ? atomicAdd(p.pool_head, tot) : 0u;
+        p.tile_count[tg] = tot;
+        p.tile_pos[tg] = base;
+        tile_base = base;
+      }
+      __syncthreads();
+      uint32_t run = tile_base;
+      for (uint32_t r = 0; r < nsl; r += kThreads) {
+        const uint32_t i = r + threadIdx.x;
         const unsigned long long key = i < nsl ? slots[i] : 0ull;
         const bool valid = key != 0ull;
         const unsigned long long mask = __ballot(valid);
-        if (mask == 0ull) continue;
-        unsigned long long pos0 = 0;
-        if (lane == 0) pos0 = atomicAdd(&p.stage_count[sidx], (unsigned long long)__popcll(mask));
-        pos0 = __shfl(pos0, 0, 64);
+        if (lane == 0) wave_sum[wave] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int v = 0; v < kWaves; ++v) {
+          before += (uint32_t)v < wave ? wave_sum[v] : 0u;
+          all += wave_sum[v];
+        }
         if (valid) {
-          const unsigned long long pos = pos0 + __popcll(mask & ((1ull << lane) - 1ull));
-          if (pos < d.stage_cap) {
+          const uint32_t pos = run + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+          if (pos < p.pool_cap) {
             const uint32_t cl = i / zmax, w = i - cl * zmax + 1;
             StageEntry e;
-            e.key = (chunk0 + cl) * zmax + (w - 1);
+            e.chunk = chunk0 + cl;
             e.bin = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
             e.power = unord_f32((uint32_t)(key >> 32));
             e.width = w;
-            p.stage[d.stage_off + pos] = e;
+            p.pool[pos] = e;
           }
         }
+        run += all;
+        __syncthreads();
       }
     } else {
       for (uint32_t i = threadIdx.x; i < nsl; i += kThreads) {
@@ -300,11 +330,14 @@ __global__ __launch_bounds__(kThreads) void bank_kernel(BankParams p) {
   }
 }
 
-static size_t lds_need(uint32_t T, uint32_t C, uint32_t zmax_max, int K, uint32_t *nseg) {
+static size_t lds_need(uint32_t T, uint32_t C, uint32_t zmax_max, int K, uint32_t *nseg,
+                       uint32_t *zc_pad) {
   const uint32_t zc = round_widths(zmax_max, K);
   const uint32_t segb = 64u * (uint32_t)K;
   *nseg = (T + zc + segb - 1) / segb;
-  return (size_t)(T / C) * zmax_max * 8u + (size_t)(*nseg) * K * kRowPitch * 4u;
+  *zc_pad = (zc + 3) / 4 * 4;
+  return (size_t)(T / C) * zmax_max * 8u + (size_t)(*zc_pad) * 4u +
+         (size_t)(*nseg) * K * kRowPitch * 4u;
 }
 
 static uint32_t gcd_u(uint32_t a, uint32_t b) {
@@ -326,14 +359,16 @@ bool choose_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, Geometry *g) {
   while (K > 1 && (C / 64) % (uint32_t)K != 0) K /= 2;
   uint64_t T = lcm_u(lcm_u(64ull * K * kWaves, C), B);
   if (T > (uint64_t)kMaxTile) return false;
-  uint32_t nseg = 0;
-  if (lds_need((uint32_t)T, C, zmax_max, K, &nseg) > kLdsBudget) return false;
-  while (T * 2 <= 4096 && lds_need((uint32_t)(T * 2), C, zmax_max, K, &nseg) <= kLdsBudget) T *= 2;
+  uint32_t nseg = 0, zcp = 0;
+  if (lds_need((uint32_t)T, C, zmax_max, K, &nseg, &zcp) > kLdsBudget) return false;
+  while (T * 2 <= 4096 && lds_need((uint32_t)(T * 2), C, zmax_max, K, &nseg, &zcp) <= kLdsBudget)
+    T *= 2;
   g->K = K;
   g->EPL = (int)(B / 64);
   g->tile = (uint32_t)T;
-  g->lds_bytes = lds_need(g->tile, C, zmax_max, K, &nseg);
+  g->lds_bytes = lds_need(g->tile, C, zmax_max, K, &nseg, &zcp);
   g->nseg_lds = nseg;
+  g->zc_max_pad = zcp;
   return true;
 }
 

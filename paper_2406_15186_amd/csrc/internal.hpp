@@ -16,7 +16,7 @@ constexpr int kWaves = 4;             // waves per workgroup of the bank kernel
 constexpr int kThreads = 64 * kWaves;
 constexpr int kRowPitch = 65;         // LDS row pitch (floats) of the power tile
 constexpr int kMaxTile = 16384;       // bins per tile
-constexpr int kSortLds = 8192;        // candidates sorted in LDS per spectrum
+constexpr uint32_t kPoolMax = 1u << 26;  // staging-pool entries per context (1 GiB)
 
 // One spectrum of a launch.  A device-resident array of these drives the
 // bank and finalise kernels; a single search is a batch of one.
@@ -24,8 +24,6 @@ struct SpecDesc {
   const float2 *x;        // complex spectrum (or, from-power mode, float power)
   const float *thr;       // per-width thresholds, zc entries (+inf beyond zmax)
   uint64_t tile_begin;    // first global tile of this spectrum
-  uint64_t stage_off;     // first staging entry of this spectrum
-  uint64_t stage_cap;     // staging entries reserved (nchunks * zmax)
   double ntrials;         // Bonferroni factor
   uint32_t n;             // bins
   uint32_t zmax;          // widths 1..zmax
@@ -33,9 +31,10 @@ struct SpecDesc {
   uint32_t nchunks;       // ceil(n / chunk)
 };
 
-// A staged candidate, written by the bank kernel in arbitrary order.
+// A staged candidate.  Each tile writes its own in (chunk, width) order to a
+// contiguous run of the staging pool.
 struct StageEntry {
-  uint32_t key;    // chunk * zmax + (width - 1): unique within a spectrum
+  uint32_t chunk;  // chunk index within the spectrum
   uint32_t bin;    // window start
   float power;     // boxcar power
   uint32_t width;  // 1..zmax
@@ -57,10 +56,14 @@ struct BankParams {
   uint32_t tile;           // T bins per tile (multiple of C, B and 64*K*kWaves)
   uint32_t zmax_max;       // largest zmax of the batch (slot row stride bound)
   uint32_t nseg_lds;       // segments of 64*K bins held in LDS (tile + halo)
+  uint32_t zc_max_pad;     // LDS floats reserved for the threshold table
   int mode;                // BankMode
   int from_power;          // x holds float power; skip normalisation
-  StageEntry *stage;       // search mode
-  unsigned long long *stage_count;  // search mode: one counter per spectrum
+  StageEntry *pool;        // search mode: staging pool
+  uint32_t pool_cap;       // entries in the pool
+  uint32_t *pool_head;     // next free pool entry (reset to 0 by the scan kernel)
+  uint32_t *tile_count;    // per tile: candidates it staged
+  uint32_t *tile_pos;      // per tile: pool offset of its first candidate
   float *M;                // tables mode: nchunks x zmax (spectrum 0 only)
   uint32_t *I;
   float *P_out;            // tables mode, optional: normalised power
@@ -73,6 +76,7 @@ struct Geometry {
   int EPL;        // normalisation elements per lane (block / 64)
   uint32_t tile;
   uint32_t nseg_lds;
+  uint32_t zc_max_pad;
   size_t lds_bytes;
 };
 
@@ -99,22 +103,35 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
                              uint32_t zc_max, double sigma, int width_search, int debug,
                              hipStream_t stream);
 
-// Sort each spectrum's staged candidates into canonical order, compute their
-// FP64 significance and write them out.  counts[s] are read, counts_next[s]
-// cleared, *total (if non-null) receives the sum of counts.
-struct FinalParams {
-  const SpecDesc *descs;           // device table, or nullptr for one spectrum
-  int nspec;
-  const StageEntry *stage;
-  const unsigned long long *counts;
-  unsigned long long *counts_next;
-  pulscan_candidate *out;
-  uint64_t capacity;
+// Exclusive scan of the per-tile candidate counts (one workgroup), the total
+// count, the staging-overflow flag, and the reset of the pool head.
+struct ScanParams {
+  const uint32_t *tile_count;
+  uint32_t *tile_prefix;           // total_tiles + 1 entries
+  uint64_t total_tiles;
+  uint32_t *pool_head;
+  uint32_t pool_cap;
   unsigned long long *total;       // device
   unsigned long long *total2;      // optional second device destination (caller's)
-  uint64_t *sort_scratch;          // >= max stage_cap entries, for lists beyond kSortLds
+  uint32_t *overflow;              // set to 1 when the pool was too small
 };
-hipError_t launch_finalise(const FinalParams &p, const SpecDesc &single, hipStream_t stream);
+hipError_t launch_scan(const ScanParams &p, hipStream_t stream);
+
+// Candidate f of the canonical order goes to out[f] (f < capacity), with its
+// FP64 significance.
+struct EmitParams {
+  const SpecDesc *descs;           // device table, or nullptr for one spectrum
+  int nspec;
+  const StageEntry *pool;
+  uint32_t pool_cap;
+  const uint32_t *tile_prefix;
+  const uint32_t *tile_pos;
+  uint64_t total_tiles;
+  pulscan_candidate *out;
+  uint64_t capacity;
+};
+hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t grid,
+                       hipStream_t stream);
 
 // Is width w searched under width_search?
 __host__ __device__ inline bool width_searched(uint32_t w, int width_search) {

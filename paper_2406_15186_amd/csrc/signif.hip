@@ -1,5 +1,6 @@
-// Significance on the device, in FP64: per-width power thresholds and the
-// finalising pass that orders the staged candidates and attaches their
+// Significance on the device, in FP64, and the passes after the bank: the
+// per-width power thresholds, the scan of the per-tile candidate counts, and
+// the emission of the candidates in canonical order with their
 // Gaussian-equivalent sigma (section 2.2.3: a width-w boxcar of chi^2(2)
 // powers is chi^2(2w); its survival probability is Bonferroni-corrected for
 // the number of trials and converted to the normal quantile).
@@ -116,95 +117,102 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
 }
 
 // ---------------------------------------------------------------------------
-// Finalise: one workgroup per spectrum.
+// Scan of the per-tile counts: one workgroup.  Thread t sums a contiguous
+// run of tiles, the run totals are scanned in LDS, and each thread writes the
+// prefixes of its run.
 
-constexpr int kFinThreads = 1024;
+constexpr int kScanThreads = 1024;
 
-__device__ unsigned long long block_sum(unsigned long long v, unsigned long long *red) {
-  // wave sum, then across the 16 waves of the workgroup
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(ScanParams p) {
+  __shared__ uint32_t part[kScanThreads];
+  const uint64_t T = p.total_tiles;
+  const uint64_t per = (T + kScanThreads - 1) / kScanThreads;
+  const uint64_t lo = (uint64_t)threadIdx.x * per;
+  const uint64_t hi = lo + per < T ? lo + per : T;
+  uint32_t sum = 0;
+  for (uint64_t t = lo; t < hi; ++t) sum += p.tile_count[t];
+  part[threadIdx.x] = sum;
   __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  unsigned long long t = 0;
-  for (int i = 0; i < kFinThreads / 64; ++i) t += red[i];
-  return t;
+  // Hillis-Steele inclusive scan of the run totals
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (uint64_t t = lo; t < hi; ++t) {
+    p.tile_prefix[t] = run;
+    run += p.tile_count[t];
+  }
+  if (threadIdx.x == kScanThreads - 1) {
+    const uint32_t total = part[kScanThreads - 1];
+    p.tile_prefix[T] = total;
+    if (p.total) *p.total = total;
+    if (p.total2) *p.total2 = total;
+    *p.overflow = *p.pool_head > p.pool_cap ? 1u : 0u;
+    *p.pool_head = 0u;
+  }
 }
 
-// In-place ascending bitonic sort of n (a power of two) 64-bit keys by the
-// whole workgroup.
-__device__ void bitonic_sort(uint64_t *a, uint32_t n) {
-  for (uint32_t k = 2; k <= n; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < n; i += kFinThreads) {
-        const uint32_t l = i ^ j;
-        if (l > i) {
-          const uint64_t x = a[i], y = a[l];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[l] = x;
-          }
-        }
+hipError_t launch_scan(const ScanParams &p, hipStream_t stream) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Emit: candidate f of the canonical order (tile order, then the tile's own
+// (chunk, width) order) is found by binary search over the tile prefixes.
+
+constexpr int kEmitThreads = 256;
+
+__global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDesc single) {
+  const uint64_t T = p.total_tiles;
+  const uint64_t total = p.tile_prefix[T];
+  const uint64_t lim = total < p.capacity ? total : p.capacity;
+  const uint64_t stride = (uint64_t)gridDim.x * kEmitThreads;
+  for (uint64_t f = (uint64_t)blockIdx.x * kEmitThreads + threadIdx.x; f < lim; f += stride) {
+    // largest t with tile_prefix[t] <= f (that tile holds candidate f)
+    uint64_t lo = 0, hi = T - 1;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi + 1) >> 1;
+      if (p.tile_prefix[mid] <= f)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const uint64_t t = lo;
+    const uint64_t idx = (uint64_t)p.tile_pos[t] + (f - p.tile_prefix[t]);
+    if (idx >= p.pool_cap) continue;  // lost to a staging overflow (reported)
+    int s = 0;
+    if (p.nspec > 1) {
+      int a = 0, b = p.nspec - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (p.descs[mid].tile_begin <= t)
+          a = mid;
+        else
+          b = mid - 1;
       }
-      __syncthreads();
+      s = a;
     }
-  }
-}
-
-__global__ __launch_bounds__(kFinThreads) void finalise_kernel(FinalParams p, SpecDesc single) {
-  __shared__ uint64_t keys[kSortLds];
-  __shared__ unsigned long long red[kFinThreads / 64];
-  const int s = blockIdx.x;
-  const SpecDesc d = p.descs ? p.descs[s] : single;
-
-  unsigned long long before = 0, all = 0;
-  for (int i = threadIdx.x; i < p.nspec; i += kFinThreads) {
-    const unsigned long long c = p.counts[i];
-    all += c;
-    if (i < s) before += c;
-  }
-  before = block_sum(before, red);
-  all = block_sum(all, red);
-  if (threadIdx.x == 0) {
-    p.counts_next[s] = 0;
-    if (s == 0) {
-      if (p.total) *p.total = all;
-      if (p.total2) *p.total2 = all;
-    }
-  }
-  unsigned long long cnt = p.counts[s];
-  if (cnt > d.stage_cap) cnt = d.stage_cap;
-  if (cnt == 0) return;
-
-  uint32_t n2 = 1;
-  while (n2 < cnt) n2 <<= 1;
-  uint64_t *a = n2 <= (uint32_t)kSortLds ? keys : p.sort_scratch + 2 * d.stage_off;
-  const StageEntry *st = p.stage + d.stage_off;
-  for (uint32_t i = threadIdx.x; i < n2; i += kFinThreads)
-    a[i] = i < cnt ? (((uint64_t)st[i].key << 32) | i) : ~0ull;
-  __syncthreads();
-  bitonic_sort(a, n2);
-
-  for (uint32_t j = threadIdx.x; j < cnt; j += kFinThreads) {
-    const unsigned long long pos = before + j;
-    if (pos >= p.capacity) break;
-    const StageEntry e = st[(uint32_t)(a[j] & 0xFFFFFFFFull)];
-    const double lp = log_sf_chi2_even((double)e.power, e.width) + log(d.ntrials);
+    const double ntrials = p.nspec > 1 ? p.descs[s].ntrials : single.ntrials;
+    const StageEntry e = p.pool[idx];
+    const double lp = log_sf_chi2_even((double)e.power, e.width) + log(ntrials);
     pulscan_candidate c;
     c.spectrum = (uint32_t)s;
     c.bin = e.bin;
     c.width = e.width;
     c.power = e.power;
     c.sigma = (float)sigma_from_logp(lp < 0.0 ? lp : 0.0);
-    c.chunk = e.key / d.zmax;
-    p.out[pos] = c;
+    c.chunk = e.chunk;
+    p.out[f] = c;
   }
 }
 
-hipError_t launch_finalise(const FinalParams &p, const SpecDesc &single, hipStream_t stream) {
-  hipLaunchKernelGGL(finalise_kernel, dim3(p.nspec), dim3(kFinThreads), 0, stream, p, single);
+hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t grid,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(emit_kernel, dim3(grid), dim3(kEmitThreads), 0, stream, p, single);
   return hipGetLastError();
 }
 

@@ -213,7 +213,7 @@ def test_invalid_arguments(ctx, pk):
         (dict(zmax=5000, chunk=256), pk.PULSCAN_EINVAL),              # zmax > nbins
         (dict(zmax=10, chunk=8192), pk.PULSCAN_EINVAL),               # block > nbins
         (dict(zmax=10, chunk=128), pk.PULSCAN_EINVAL),                # MoM block not 4^k
-        (dict(zmax=10, chunk=320, opts=pk.make_opts(norm_block=256)), pk.PULSCAN_EUNSUPPORTED),
+        (dict(zmax=10, chunk=100, opts=pk.make_opts(norm_block=64)), pk.PULSCAN_EUNSUPPORTED),
         (dict(zmax=10, chunk=256, opts=pk.make_opts(norm=pk.PULSCAN_NORM_EXACT)),
          pk.PULSCAN_EUNSUPPORTED),
         (dict(zmax=10, chunk=16), pk.PULSCAN_EUNSUPPORTED),           # valid 4^k, below 64
