@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--workload", default="plain_2e23")
     ap.add_argument("--latency-calls", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense", action="store_true",
+                    help="evaluate every width block (no pruning bound): same candidates")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the search shards by "
@@ -71,7 +73,7 @@ def main():
 
     ref, ref_count = ctx.pulscan_search_ex(d, Z, C, sigma)
     log(f"bench: {ref_count} candidates per step")
-    opts = pk.make_opts(async_=True, stream=stream)
+    opts = pk.make_opts(async_=True, stream=stream, dense=args.dense)
 
     def step():
         ctx.pulscan_search_ex(d, Z, C, sigma, capacity=cap, opts=opts, out_device=out_buf,
@@ -109,15 +111,25 @@ def main():
     for _ in range(args.latency_calls):
         torch.cuda.synchronize()
         a = time.perf_counter()
-        ctx.pulscan_search_ex(d, Z, C, sigma, capacity=cap)
+        ctx.pulscan_search_ex(d, Z, C, sigma, capacity=cap, opts=pk.make_opts(dense=args.dense))
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat)
 
-    achieved = n * Z * BANK_OPS_PER_BIN_WIDTH / (bank_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                "kernel": "bank_kernel", "kernel_us": round(bank_ms * 1e3, 2),
-                "ops_per_bin_width": BANK_OPS_PER_BIN_WIDTH}
+    if args.dense:
+        # every width evaluated: bounded by the VALU work of the recursion
+        achieved = n * Z * BANK_OPS_PER_BIN_WIDTH / (bank_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                    "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
+                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                    "kernel": "bank_kernel", "kernel_us": round(bank_ms * 1e3, 2),
+                    "ops_per_bin_width": BANK_OPS_PER_BIN_WIDTH}
+    else:
+        # pruned bank: one read of the complex spectrum, 8 bytes per bin
+        achieved = 8.0 * n / (bank_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "bank_kernel", "kernel_us": round(bank_ms * 1e3, 2),
+                    "bytes_per_bin": 8}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -140,7 +152,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "nbins": n, "zmax": Z, "chunk": C, "sigma": sigma,
-                   "tones": len(tones), "red_frac": wl.red_frac, "path": "plain, async"},
+                   "tones": len(tones), "red_frac": wl.red_frac,
+                   "path": "plain, async, " + ("dense" if args.dense else "pruned")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hbm_frac_step": round(8.0 * n / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),

@@ -110,6 +110,10 @@ typedef struct {
                            1: enqueue only; needs out->on_device and
                            out->count_device                                         */
   void *stream;         /* hipStream_t to run on; NULL = the null (default) stream */
+  int32_t dense;        /* 0 (default): skip width blocks that a running upper bound
+                           proves cannot reach their threshold (exact: the same
+                           candidates).  1: evaluate every width block            */
+  int32_t reserved;
 } pulscan_opts;
 
 typedef struct pulscan_ctx pulscan_ctx;
@@ -144,7 +148,9 @@ int pulscan_search(const pulscan_complex *spectrum, size_t nbins, int zmax, int 
                    float sigma_thresh, pulscan_candidates *out);
 
 /* pulscan_search on an explicit context with options (opts NULL = defaults).
- * chunk must be a multiple of 64 (at most 16384); see pulscan_opts for the
+ * The GPU kernels take chunk a multiple of 64 (at most 16384), zmax <= 4096
+ * and a tile that fits in 64 KiB of LDS (chunk * zmax is the main term);
+ * other valid shapes return PULSCAN_EUNSUPPORTED.  See pulscan_opts for the
  * normalisation block. */
 int pulscan_search_ex(pulscan_ctx *ctx, const pulscan_complex *spectrum, size_t nbins, int zmax,
                       int chunk, float sigma_thresh, const pulscan_opts *opts,

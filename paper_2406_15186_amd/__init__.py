@@ -50,12 +50,13 @@ class pulscan_candidates(ctypes.Structure):
 class pulscan_opts(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int32), ("norm_block", ctypes.c_int32),
                 ("ntrials", ctypes.c_double), ("width_search", ctypes.c_int32),
-                ("async_", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("async_", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("dense", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(pulscan_candidate) == 24 == CANDIDATE_DTYPE.itemsize
 assert ctypes.sizeof(pulscan_candidates) == 40
-assert ctypes.sizeof(pulscan_opts) == 32
+assert ctypes.sizeof(pulscan_opts) == 40
 
 # every function the header declares: name -> (restype, argtypes)
 _vp, _sz, _i, _f, _d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float, ctypes.c_double
@@ -140,10 +141,11 @@ def pulscan_opts_default() -> pulscan_opts:
 
 
 def make_opts(norm: int = PULSCAN_NORM_MOM, norm_block: int = 0, ntrials: float = 0.0,
-              width_search: int = PULSCAN_W_ALL, async_: bool = False, stream=None) -> pulscan_opts:
+              width_search: int = PULSCAN_W_ALL, async_: bool = False, stream=None,
+              dense: bool = False) -> pulscan_opts:
     o = pulscan_opts_default()
     o.norm, o.norm_block, o.ntrials = norm, norm_block, ntrials
-    o.width_search, o.async_ = width_search, int(bool(async_))
+    o.width_search, o.async_, o.dense = width_search, int(bool(async_)), int(bool(dense))
     if stream is not None:
         o.stream = stream if isinstance(stream, int) else stream.cuda_stream
     return o

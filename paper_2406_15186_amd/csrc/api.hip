@@ -146,6 +146,7 @@ int check_spectrum(const void *x, uint64_t n, int zmax, int chunk, const pulscan
   if (o.width_search != PULSCAN_W_ALL && o.width_search != PULSCAN_W_LOG2) return PULSCAN_EINVAL;
   if (o.norm_block < 0) return PULSCAN_EINVAL;
   if (!(o.ntrials == 0.0 || (isfinite(o.ntrials) && o.ntrials >= 1.0))) return PULSCAN_EINVAL;
+  if (o.dense != 0 && o.dense != 1) return PULSCAN_EINVAL;
   const uint64_t B = o.norm_block > 0 ? (uint64_t)o.norm_block : (uint64_t)chunk;
   if (n < B || n < (uint64_t)zmax) return PULSCAN_EINVAL;
   if (o.norm == PULSCAN_NORM_MOM && !is_pow4(B)) return PULSCAN_EINVAL;
@@ -207,9 +208,13 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   const int ws = debug ? PULSCAN_W_ALL : a.opts.width_search;
 
   uint32_t zmax_max = 0;
-  for (const SpecIn &s : specs) zmax_max = s.zmax > zmax_max ? s.zmax : zmax_max;
+  uint64_t n_min = ~0ull;
+  for (const SpecIn &s : specs) {
+    zmax_max = s.zmax > zmax_max ? s.zmax : zmax_max;
+    n_min = s.n < n_min ? s.n : n_min;
+  }
   Geometry g;
-  if (!choose_geometry(a.chunk, a.block, zmax_max, &g)) return PULSCAN_EUNSUPPORTED;
+  if (!choose_geometry(a.chunk, a.block, zmax_max, n_min, &g)) return PULSCAN_EUNSUPPORTED;
 
   // descriptors
   std::vector<SpecDesc> descs(nspec);
@@ -278,6 +283,7 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   bp.zc_max_pad = g.zc_max_pad;
   bp.mode = debug ? kModeTables : kModeSearch;
   bp.from_power = a.kind == kRunFromPower ? 1 : 0;
+  bp.dense = a.opts.dense ? 1 : 0;
   bp.M = a.M;
   bp.I = a.I;
   bp.P_out = a.P_out;

@@ -12,9 +12,7 @@ namespace pulscan {
 // deviation (section 2.2.3).
 constexpr float kMadScale = 1.482602218505602f;
 
-constexpr int kWaves = 4;             // waves per workgroup of the bank kernel
-constexpr int kThreads = 64 * kWaves;
-constexpr int kRowPitch = 65;         // LDS row pitch (floats) of the power tile
+constexpr int kMaxThreads = 512;      // threads per workgroup of the bank kernel (<= 8 waves)
 constexpr int kMaxTile = 16384;       // bins per tile
 constexpr uint32_t kPoolMax = 1u << 26;  // staging-pool entries per context (1 GiB)
 
@@ -53,12 +51,13 @@ struct BankParams {
   uint64_t total_tiles;
   uint32_t chunk;          // C
   uint32_t block;          // normalisation block B
-  uint32_t tile;           // T bins per tile (multiple of C, B and 64*K*kWaves)
+  uint32_t tile;           // T bins per tile (multiple of C, B and 64*K*waves)
   uint32_t zmax_max;       // largest zmax of the batch (slot row stride bound)
   uint32_t nseg_lds;       // segments of 64*K bins held in LDS (tile + halo)
   uint32_t zc_max_pad;     // LDS floats reserved for the threshold table
   int mode;                // BankMode
   int from_power;          // x holds float power; skip normalisation
+  int dense;               // 1: skip the pruning bound (every width block evaluated)
   StageEntry *pool;        // search mode: staging pool
   uint32_t pool_cap;       // entries in the pool
   uint32_t *pool_head;     // next free pool entry (reset to 0 by the scan kernel)
@@ -74,15 +73,18 @@ struct BankParams {
 struct Geometry {
   int K;          // bins per lane in the bank
   int EPL;        // normalisation elements per lane (block / 64)
+  int waves;      // waves per workgroup
   uint32_t tile;
   uint32_t nseg_lds;
   uint32_t zc_max_pad;
   size_t lds_bytes;
 };
 
-// Geometry for chunk C, block B and the largest width zc (rounded); returns
-// false when the kernels cannot run it (too large for LDS, bad sizes).
-bool choose_geometry(uint32_t chunk, uint32_t block, uint32_t zmax_max, Geometry *g);
+// Geometry for chunk C, block B, the largest zmax of the launch and the
+// shortest spectrum (n_hint, to keep enough tiles); returns false when the
+// kernels cannot run it (too large for LDS, bad sizes, zmax > 4096).
+bool choose_geometry(uint32_t chunk, uint32_t block, uint32_t zmax_max, uint64_t n_hint,
+                     Geometry *g);
 
 // Round zmax up to the width block of the bank kernel for K bins per lane.
 inline uint32_t round_widths(uint32_t zmax, int K) { return (zmax + K - 1) / K * K; }

@@ -63,9 +63,9 @@ int main(void) {
          offsetof(pulscan_candidate, sigma), offsetof(pulscan_candidate, chunk));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(pulscan_candidates, capacity), offsetof(pulscan_candidates, count),
          offsetof(pulscan_candidates, on_device), offsetof(pulscan_candidates, count_device), sizeof(pulscan_complex));
-  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_opts, norm), offsetof(pulscan_opts, norm_block),
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_opts, norm), offsetof(pulscan_opts, norm_block),
          offsetof(pulscan_opts, ntrials), offsetof(pulscan_opts, width_search),
-         offsetof(pulscan_opts, async), offsetof(pulscan_opts, stream));
+         offsetof(pulscan_opts, async), offsetof(pulscan_opts, stream), offsetof(pulscan_opts, dense));
   return 0;
 }
 """)
@@ -85,7 +85,7 @@ int main(void) {
     O = pk.pulscan_opts
     assert [int(v) for v in lines[3].split()] == [O.norm.offset, O.norm_block.offset,
                                                   O.ntrials.offset, O.width_search.offset,
-                                                  O.async_.offset, O.stream.offset]
+                                                  O.async_.offset, O.stream.offset, O.dense.offset]
     assert [d[0] for d in pk.CANDIDATE_DTYPE.descr] == [f[0] for f in C._fields_]
 
 
@@ -96,8 +96,8 @@ def test_strerror_and_default_options(L):
     assert "capacity" in pk.pulscan_strerror(-3)
     assert pk.pulscan_strerror(12345) == "unknown status"
     o = pk.pulscan_opts_default()
-    assert (o.norm, o.norm_block, o.ntrials, o.width_search, o.async_, o.stream) == \
-        (pk.PULSCAN_NORM_MOM, 0, 0.0, pk.PULSCAN_W_ALL, 0, None)
+    assert (o.norm, o.norm_block, o.ntrials, o.width_search, o.async_, o.stream, o.dense) == \
+        (pk.PULSCAN_NORM_MOM, 0, 0.0, pk.PULSCAN_W_ALL, 0, None, 0)
 
 
 def test_null_arguments_are_rejected_without_a_device(L):

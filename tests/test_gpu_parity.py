@@ -315,3 +315,68 @@ def test_kernel_timing_records_launches(ctx, oracle_lib):
     ms, k = ctx.pulscan_ctx_kernel_time()
     ctx.pulscan_ctx_set_timing(False)
     assert k == 3 and ms > 0
+
+
+# ------------------------------------------------- pruning is exact --------
+
+def _pruned_vs_dense(ctx, pk, x, Z, C, sigma=6.0, label=""):
+    d = to_device(x)
+    a, na = ctx.pulscan_search_ex(d, Z, C, sigma)
+    b, nb = ctx.pulscan_search_ex(d, Z, C, sigma, opts=pk.make_opts(dense=True))
+    assert na == nb, (label, na, nb)
+    assert a.tobytes() == b.tobytes(), label
+    return na
+
+
+@pytest.mark.parametrize("name", ["plain_2e16", "plain_2e23"])
+def test_pruned_equals_dense_workloads(ctx, pk, oracle_lib, name):
+    wl = synth.workload(name)
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    say(f"pruned vs dense {name}")
+    n = _pruned_vs_dense(ctx, pk, x, wl.zmax, wl.chunk, wl.sigma, name)
+    assert n > 0
+
+
+def test_pruned_equals_dense_near_threshold(ctx, pk, oracle_lib):
+    """Many seeds with tones whose matched boxcar sits near the threshold, so
+    many per-chunk maxima fall just either side of it."""
+    import dataclasses
+    base = synth.workload("plain_2e16")
+    wl = dataclasses.replace(base, n_tones=40, z_choices=None, z_range=(1, 200), A_range=(5.5, 6.5),
+                             r_range=(0, (1 << 16) - 202))
+    total = 0
+    for spawn in range(12):
+        x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, spawn=spawn)
+        for Z, C in ((64, 256), (200, 1024), (130, 64)):
+            total += _pruned_vs_dense(ctx, pk, x, Z, C, 6.0, f"seed {spawn} Z={Z} C={C}")
+    say(f"  {total} candidates compared")
+    assert total > 0
+
+
+def test_pruned_at_tile_edges_and_spectrum_end(ctx, pk, oracle_lib):
+    """Wide tones straddling every tile boundary and ending at the last bin:
+    the pruning bound must hold across halos and the spectrum's end."""
+    rng = np.random.default_rng(99)
+    for n, Z, C in ((3 * 4096 + 777, 200, 1024), (2 * 4096 + 300, 64, 256), (5000, 150, 64)):
+        x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+        for edge in list(range(4096, n, 4096)) + [n]:
+            for w, amp in ((190, 1.6), (30, 3.0), (5, 6.0)):
+                lo = max(edge - w // 2, 0) if edge < n else n - w
+                x[lo:lo + w] += np.complex64(amp)
+        _pruned_vs_dense(ctx, pk, x, Z, C, 6.0, f"edges n={n} Z={Z} C={C}")
+        cands, _ = ctx.pulscan_search_ex(to_device(x), Z, C, 6.0)
+        orc = oracle_lib.search(x, Z, C, 6.0, tables=True)
+        compare_candidates(cands, orc, orc.P, float(n * Z), 6.0, oracle_lib, f"edges n={n}")
+        assert len(cands) > 0
+
+
+def test_pruned_equals_dense_batched(ctx, pk, oracle_lib):
+    wl = synth.workload("plain_2e16")
+    specs, zs = [], []
+    for s, (n, Z) in enumerate([(1 << 16, 64), (50000, 200), (70001, 37), (4096, 1)]):
+        x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, spawn=s, nbins=n)
+        specs.append(to_device(x))
+        zs.append(Z)
+    a, na, _ = ctx.pulscan_search_batched(specs, zs, 1024, 6.0)
+    b, nb, _ = ctx.pulscan_search_batched(specs, zs, 1024, 6.0, opts=pk.make_opts(dense=True))
+    assert na == nb and a.tobytes() == b.tobytes()
