@@ -31,6 +31,24 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BANK_OPS_PER_BIN_WIDTH = 1.5
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bank_kernel_plain_2e23_traffic.json")
+BANK_SOURCE = os.path.join(ROOT, "paper_2406_15186_amd", "csrc", "bank.hip")
+
+
+def measured_traffic():
+    """HBM bytes per bank-kernel launch from the committed counter summary, or
+    None when there is none or the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    src = hashlib.sha256(open(BANK_SOURCE, "rb").read()).hexdigest()
+    if rec.get("bank_source_sha256") != src:
+        return None
+    return int(rec["bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -45,6 +63,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dense", action="store_true",
                     help="evaluate every width block (no pruning bound): same candidates")
+    ap.add_argument("--copy-reference-mib", type=int, default=0,
+                    help="after timing, copy a buffer of this many MiB once on the device, so "
+                         "that hardware byte counters can be scaled by a copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the search shards by "
@@ -113,7 +134,17 @@ def main():
         a = time.perf_counter()
         ctx.pulscan_search_ex(d, Z, C, sigma, capacity=cap, opts=pk.make_opts(dense=args.dense))
         lat.append((time.perf_counter() - a) * 1e3)
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.zeros(1)
+
+    if args.copy_reference_mib > 0:
+        nb = args.copy_reference_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_reference_mib} MiB device to device")
+        del src, dst
 
     if args.dense:
         # every width evaluated: bounded by the VALU work of the recursion
@@ -127,7 +158,7 @@ def main():
         # pruned bank: one read of the complex spectrum, 8 bytes per bin
         achieved = 8.0 * n / (bank_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "kernel": "bank_kernel", "kernel_us": round(bank_ms * 1e3, 2),
                     "bytes_per_bin": 8}
 
