@@ -37,7 +37,8 @@ struct ThrKey {
 
 struct pulscan_ctx {
   int device = 0;
-  DevBuf thr, pool, tile_count, tile_pos, tile_prefix, counters, outbuf, descs, jobs;
+  DevBuf thr, pool, tile_word, tile_prefix, counters, outbuf, descs, jobs;
+  uint32_t gen = 0;  // launch generation of the per-tile count words
   ThrKey thr_key;
   // pinned staging of batched descriptors / threshold jobs
   void *pinned = nullptr;
@@ -53,12 +54,15 @@ struct pulscan_ctx {
 
 namespace {
 
-// Device-resident counters of a search; zeroed when allocated, the pool head
-// is reset by the scan kernel at the end of every search.
+// Device-resident counters of a search; zeroed when allocated.  The bank
+// kernel's last workgroup re-arms the pool head and the finished-tile count
+// at the end of every search.
 struct Counters {
   unsigned long long total;
   uint32_t overflow;
   uint32_t head;
+  uint32_t done;
+  uint32_t pad;
 };
 
 #define HIP_TRY(call)                       \
@@ -298,9 +302,7 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   if (!debug) {
     st = grow(ctx, ctx->pool, (size_t)pool_cap * sizeof(StageEntry), false);
     if (st) return st;
-    st = grow(ctx, ctx->tile_count, tiles * sizeof(uint32_t), false);
-    if (st) return st;
-    st = grow(ctx, ctx->tile_pos, tiles * sizeof(uint32_t), false);
+    st = grow(ctx, ctx->tile_word, tiles * sizeof(unsigned long long), true);
     if (st) return st;
     st = grow(ctx, ctx->tile_prefix, (tiles + 1) * sizeof(uint32_t), false);
     if (st) return st;
@@ -310,8 +312,14 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
     bp.pool = static_cast<StageEntry *>(ctx->pool.p);
     bp.pool_cap = pool_cap;
     bp.pool_head = &cnt->head;
-    bp.tile_count = static_cast<uint32_t *>(ctx->tile_count.p);
-    bp.tile_pos = static_cast<uint32_t *>(ctx->tile_pos.p);
+    bp.done = &cnt->done;
+    bp.tile_word = static_cast<unsigned long long *>(ctx->tile_word.p);
+    if (++ctx->gen == 0) ctx->gen = 1;  // words start at generation 0
+    bp.gen = ctx->gen;
+    bp.tile_prefix = static_cast<uint32_t *>(ctx->tile_prefix.p);
+    bp.total = &cnt->total;
+    bp.total2 = reinterpret_cast<unsigned long long *>(a.out->count_device);
+    bp.overflow = &cnt->overflow;
   }
 
   if (nspec > 1) {
@@ -355,24 +363,14 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
     if (st) return st;
     dst = static_cast<pulscan_candidate *>(ctx->outbuf.p);
   }
-  ScanParams sp{};
-  sp.tile_count = bp.tile_count;
-  sp.tile_prefix = static_cast<uint32_t *>(ctx->tile_prefix.p);
-  sp.total_tiles = tiles;
-  sp.pool_head = &cnt->head;
-  sp.pool_cap = pool_cap;
-  sp.total = &cnt->total;
-  sp.total2 = reinterpret_cast<unsigned long long *>(out->count_device);
-  sp.overflow = &cnt->overflow;
-  HIP_TRY(launch_scan(sp, stream));
   EmitParams ep{};
   ep.descs = nspec > 1 ? bp.descs : nullptr;
   ep.nspec = nspec;
   ep.pool = bp.pool;
   ep.pool_cap = pool_cap;
-  ep.tile_prefix = sp.tile_prefix;
-  ep.tile_pos = bp.tile_pos;
-  ep.total_tiles = tiles;
+  ep.tile_prefix = bp.tile_prefix;
+  ep.total = bp.total;
+  ep.chunk = a.chunk;
   ep.out = dst;
   ep.capacity = cap;
   const uint64_t work = cap < worst ? cap : worst;
@@ -386,6 +384,7 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   HIP_TRY(hipStreamSynchronize(stream));
   const unsigned long long total = hc.total;
   out->count = total;
+  if (hc.overflow == 2) return PULSCAN_EHIP;  // a tile's count never arrived
   if (hc.overflow) return PULSCAN_ENOMEM;
   if (!out->on_device) {
     const uint64_t ncopy = total < cap ? total : cap;
@@ -447,7 +446,7 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DevBuf *bufs[] = {&ctx->thr,         &ctx->pool,     &ctx->tile_count, &ctx->tile_pos,
+  DevBuf *bufs[] = {&ctx->thr,         &ctx->pool,     &ctx->tile_word,
                     &ctx->tile_prefix, &ctx->counters, &ctx->outbuf,     &ctx->descs,
                     &ctx->jobs};
   for (DevBuf *b : bufs)

@@ -12,12 +12,14 @@
 //    holds its T bins plus a halo of up to zmax - 1 bins from the next blocks
 //    (normalised with those blocks' own statistics).
 //  * Bank (section 2.2.5): each lane owns K consecutive window starts.  A
-//    running upper bound first finds the first width block in which any of
-//    the wave's windows could reach its threshold (powers are non-negative,
-//    so a lane's union window bounds all its windows); a wave that cannot
-//    reach any threshold is done.  Otherwise the wave runs the exact
-//    recursion Y_w = Y_{w-1} + P[i+w-1] in registers from width 1, testing
-//    the thresholds from that block on.  Both routes give the same result.
+//    running upper bound finds, per lane, the first width block in which one
+//    of its windows could reach its threshold (powers are non-negative, so a
+//    lane's union window bounds all its windows, and thresholds rise with
+//    the width).  Lanes that can reach one are queued; the whole workgroup
+//    then evaluates every (queued lane, width block) exactly, each unit
+//    entering its block from the K-bin group sums.  The sums follow one
+//    canonical FP32 order (see width_block) in both this pruned route and
+//    the dense route, which evaluates everything; both give the same bits.
 //  * Per-chunk maxima (appendix algorithm "Boxcar Filtering Process"): a lane
 //    compares the maximum of its K sums with the width's threshold; when it
 //    reaches it, the lane finds its first bin attaining that maximum and
@@ -108,16 +110,27 @@ __device__ __forceinline__ void wave_mom2(float (&a)[EPL], float (&b)[EPL], floa
 }
 
 // The same for one set of values (the trees of blocks of 1024 bins or more
-// run one at a time to stay within the register budget of 4 waves per SIMD).
-template <int EPL>
-__device__ __forceinline__ float wave_mom1(float (&a)[EPL]) {
+// run one at a time to stay within the register budget).
+template <int EPL, bool DEV>
+__device__ __forceinline__ float wave_mom1(const float (&a)[EPL], float c) {
+  // first level straight from the inputs (f(x) = x, or |x - c| for the MAD),
+  // so the inputs need no working copy
+  constexpr int Q = EPL / 4;
+  float v[Q];
 #pragma unroll
-  for (int cnt = EPL; cnt >= 4; cnt /= 4) {
+  for (int m = 0; m < Q; ++m) {
+    float e[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e[j] = DEV ? fabsf(a[m + j * Q] - c) : a[m + j * Q];
+    v[m] = m4x2(e[0], e[1], e[2], e[3]);
+  }
+#pragma unroll
+  for (int cnt = Q; cnt >= 4; cnt /= 4) {
     const int q = cnt / 4;
 #pragma unroll
-    for (int m = 0; m < q; ++m) a[m] = m4x2(a[m], a[m + q], a[m + 2 * q], a[m + 3 * q]);
+    for (int m = 0; m < q; ++m) v[m] = m4x2(v[m], v[m + q], v[m + 2 * q], v[m + 3 * q]);
   }
-  float x = a[0];
+  float x = v[0];
   {
     const float x1 = from_plus16(x);
     x = m4x2(x, x1, from_plus32(x), from_plus32(x1));
@@ -213,19 +226,10 @@ __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, 
   const uint32_t own = bd.own, s0 = bd.s0;
   float med_re, med_im, mad_re, mad_im;
   if constexpr (EPL >= 16) {
-    float w[EPL];
-#pragma unroll
-    for (int m = 0; m < EPL; ++m) w[m] = re[m];
-    med_re = wave_mom1<EPL>(w);
-#pragma unroll
-    for (int m = 0; m < EPL; ++m) w[m] = im[m];
-    med_im = wave_mom1<EPL>(w);
-#pragma unroll
-    for (int m = 0; m < EPL; ++m) w[m] = fabsf(re[m] - med_re);
-    mad_re = wave_mom1<EPL>(w);
-#pragma unroll
-    for (int m = 0; m < EPL; ++m) w[m] = fabsf(im[m] - med_im);
-    mad_im = wave_mom1<EPL>(w);
+    med_re = wave_mom1<EPL, false>(re, 0.f);
+    med_im = wave_mom1<EPL, false>(im, 0.f);
+    mad_re = wave_mom1<EPL, true>(re, med_re);
+    mad_im = wave_mom1<EPL, true>(im, med_im);
   } else {
     float wa[EPL], wb[EPL];
 #pragma unroll
@@ -276,6 +280,16 @@ __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, 
   }
 }
 
+// threadIdx.x passed through an empty asm statement.  Each phase of the bank
+// kernel derives its lane addresses from its own copy, so the compiler
+// recomputes them there instead of keeping them live (and spilled) across
+// the whole kernel.
+__device__ __forceinline__ uint32_t fresh_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // A wave-uniform pointer in the constant address space: loads through it
 // with uniform indices become scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const float *const_fptr;
@@ -286,62 +300,110 @@ __device__ __forceinline__ const_fptr uniform_const(const float *p) {
   return (const_fptr)(((uint64_t)hi << 32) | lo);
 }
 
+// Canonical FP32 order of a boxcar sum.  A tile is cut into groups of K
+// bins (the bins one lane owns).  The window [i, i + w) is summed as
+//   Y = hb + t,
+// where t adds the bins of the window's last, unfinished group in increasing
+// order starting from zero, and hb adds, in order, the partial sum of the
+// first group (bins i .. end of i's group, increasing, from zero) and the
+// sums of the whole groups in between (each added in increasing order from
+// zero, exactly as the K-bin group sums of the pruning bound).  Carried from
+// width to width this is the recursion of section 2.2.5 with one extra
+// addition: t += P[i + w - 1], Y = hb + t, and when the window ends on a
+// group boundary hb = Y, t = 0.  Any width block can be entered from the
+// group sums alone, so the exact pass can split one lane's widths over many
+// threads; the dense and the pruned routes both use this order and agree bit
+// for bit.  (Sums of non-negative terms: every order is within (w-1) u of
+// the exact sum, as the recursion's.)
+
+// Starts handled together by one thread: a lane's K starts are taken KS at
+// a time, which keeps the running state within the register budget of six
+// waves per SIMD.
+template <int K>
+constexpr int ks_of() {
+  return K < 8 ? K : 8;
+}
+
+// Load the KS + K - 1 powers P[b0 + k0 + wb + j] (j < KS + K - 1) that the
+// starts k0 .. k0+KS-1 of lane L (b0 = L*K) read in width block wb+1 ..
+// wb+K.  They lie in lane columns L + wb/K and L + wb/K + 1.
+template <int K>
+__device__ __forceinline__ void load_window(const float *__restrict__ Pl, uint32_t L, uint32_t wb,
+                                            int k0, float (&q)[ks_of<K>() + K - 1]) {
+  constexpr int PITCH = pitch_of<K>();
+  constexpr int KS = ks_of<K>();
+  const uint32_t La = L + wb / K, Lb = La + 1;
+  const float *pa = Pl + (La >> 6) * (K * PITCH) + (La & 63);
+  const float *pb = Pl + (Lb >> 6) * (K * PITCH) + (Lb & 63);
+#pragma unroll
+  for (int j = 0; j < KS + K - 1; ++j) {
+    const int r = k0 + j;  // k0 is a multiple of KS, known at compile time after unrolling
+    q[j] = r < K ? pa[r * PITCH] : pb[(r - K) * PITCH];
+  }
+}
+
+// One width block wb+1 .. wb+K (wb a multiple of K) for starts k0 .. k0+KS-1
+// of a lane: q[j] = P[b0 + k0 + wb + j], hb and t the state of those starts
+// after width wb.  The maximum over the KS starts of each width is compared
+// with the width's threshold Tv[u] and merged into the chunk's slot (larger
+// power wins, then the smaller bin).
+template <int K, typename TV>
+__device__ __forceinline__ void width_block(const float (&q)[ks_of<K>() + K - 1],
+                                            float (&hb)[ks_of<K>()], float (&t)[ks_of<K>()],
+                                            int k0, const TV &Tv, uint32_t wb, uint32_t zmax,
+                                            unsigned long long *slot_row, uint32_t bin0) {
+  constexpr int KS = ks_of<K>();
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int c = K - 1 - u - k0;  // the start whose window ends on a group boundary
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      t[k] += q[k + u];
+      const float y = hb[k] + t[k];
+      m = fmaxf(m, y);
+      if (k == c) {
+        hb[k] = y;
+        t[k] = 0.f;
+      }
+    }
+    if (m >= Tv[u]) {
+      const uint32_t w = wb + u + 1;
+      if (w <= zmax) {
+        // hb + t is each start's sum again (hb + 0 for the folded start)
+        uint32_t kk = KS - 1;
+#pragma unroll
+        for (int k = KS - 2; k >= 0; --k) kk = (hb[k] + t[k] == m) ? (uint32_t)k : kk;
+        const unsigned long long key =
+            ((unsigned long long)ord_f32(m) << 32) | (0xFFFFFFFFu - (bin0 + k0 + kk));
+        atomicMax(&slot_row[w - 1], key);
+      }
+    }
+  }
+}
+
 // The exact bank over one segment of 64*K window starts (segment g of the
-// tile), lane l owning starts g*64K + l*K .. +K-1: the running sums of
-// section 2.2.5 for every width, and from width block `first` on, the
-// per-lane maximum, the threshold test and the merge into the chunk's slot.
+// tile), lane l owning starts g*64K + l*K .. +K-1: every width 1..zc in the
+// canonical order, with the per-lane maximum, the threshold test and the
+// merge into the chunk's slot for every width.
 template <int K>
 __device__ __forceinline__ void bank_dense(const float *__restrict__ Pl, uint32_t g, uint32_t lane,
                                            const_fptr thr, uint32_t zmax, uint32_t zc,
-                                           uint32_t first, unsigned long long *slot_row,
-                                           uint32_t bin0) {
-  constexpr int PITCH = pitch_of<K>();
-  float s[K], q[2 * K];
+                                           unsigned long long *slot_row, uint32_t bin0) {
+  constexpr int KS = ks_of<K>();
+  const uint32_t L = g * 64 + lane;
 #pragma unroll
-  for (int k = 0; k < K; ++k) s[k] = 0.f;
-  {
-    const float *bp = Pl + g * (K * PITCH) + lane;
+  for (int k0 = 0; k0 < K; k0 += KS) {
+    float hb[KS], t[KS], q[KS + K - 1];
 #pragma unroll
-    for (int v = 0; v < K; ++v) q[v] = bp[v * PITCH];
-  }
-  for (uint32_t wb = 0; wb < zc; wb += K) {
-    // q[j] = P[start + wb + j], j < 2K: fetch the upper half
-    {
-      const uint32_t L = lane + wb / K + 1;
-      const float *bp = Pl + (g + (L >> 6)) * (K * PITCH) + (L & 63);
-#pragma unroll
-      for (int v = 0; v < K; ++v) q[K + v] = bp[v * PITCH];
-    }
-    if (wb < first * K) {
-      // widths below the first block that can reach a threshold: sums only
-#pragma unroll
-      for (int u = 0; u < K; ++u)
-#pragma unroll
-        for (int k = 0; k < K; ++k) s[k] += q[k + u];
-    } else {
+    for (int k = 0; k < KS; ++k) hb[k] = t[k] = 0.f;
+    for (uint32_t wb = 0; wb < zc; wb += K) {
+      load_window<K>(Pl, L, wb, k0, q);
       float Tv[K];  // this block's thresholds (scalar loads)
 #pragma unroll
       for (int u = 0; u < K; ++u) Tv[u] = thr[wb + u];
-#pragma unroll
-      for (int u = 0; u < K; ++u) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) s[k] += q[k + u];  // width wb+u+1
-        const float m = max_of<K>(s);
-        if (m >= Tv[u]) {
-          const uint32_t w = wb + u + 1;
-          if (w <= zmax) {
-            uint32_t kk = K - 1;
-#pragma unroll
-            for (int k = K - 2; k >= 0; --k) kk = (s[k] == m) ? (uint32_t)k : kk;
-            const unsigned long long key =
-                ((unsigned long long)ord_f32(m) << 32) | (0xFFFFFFFFu - (bin0 + kk));
-            atomicMax(&slot_row[w - 1], key);
-          }
-        }
-      }
+      width_block<K>(q, hb, t, k0, Tv, wb, zmax, slot_row, bin0);
     }
-#pragma unroll
-    for (int v = 0; v < K; ++v) q[v] = q[K + v];
   }
 }
 
@@ -367,27 +429,21 @@ __device__ __forceinline__ uint32_t bound_lane(const float *__restrict__ Pl,
                                                const float *__restrict__ Tb, uint32_t nblk) {
   constexpr int PITCH = pitch_of<K>();
   constexpr int S = K < kSub ? K : kSub;
-  float q[2 * K];
-  {
-    const float *bp = Pl + g * (K * PITCH) + lane;
-#pragma unroll
-    for (int v = 0; v < K; ++v) q[v] = bp[v * PITCH];
-    const uint32_t L = lane + 1;
-    const float *bq = Pl + (g + (L >> 6)) * (K * PITCH) + (L & 63);
-#pragma unroll
-    for (int v = 0; v < K - 1; ++v) q[K + v] = bq[v * PITCH];
-  }
-  if (CLAMP) {
-#pragma unroll
-    for (int j = 0; j < 2 * K - 1; ++j) q[j] = fmaxf(q[j], 0.f);
-  }
+  // the lane's first 2K - 1 bins, summed as they are read
+  const float *bp = Pl + g * (K * PITCH) + lane;
+  const uint32_t L1 = lane + 1;
+  const float *bq = Pl + (g + (L1 >> 6)) * (K * PITCH) + (L1 & 63);
   float U = 0.f;
 #pragma unroll
-  for (int j = 0; j < K - 1; ++j) U += q[j];
+  for (int j = 0; j < K - 1; ++j) {
+    const float v = bp[j * PITCH];
+    U += CLAMP ? fmaxf(v, 0.f) : v;
+  }
   bool hit = false;
 #pragma unroll
   for (int u = 0; u < K; ++u) {
-    U += q[K - 1 + u];
+    const float v = u == 0 ? bp[(K - 1) * PITCH] : bq[(u - 1) * PITCH];
+    U += CLAMP ? fmaxf(v, 0.f) : v;
     if ((u + 1) % S == 0) hit = hit || (U >= Tb1[u / S]);
   }
   uint32_t fl = hit ? 0u : nblk;
@@ -401,51 +457,117 @@ __device__ __forceinline__ uint32_t bound_lane(const float *__restrict__ Pl,
   return fl;
 }
 
-// Exact evaluation of KF consecutive window starts [st, st + KF) of the tile
-// (one work item of the cooperative pass): the running sums of section 2.2.5
-// from width 1, with the threshold test from width wfirst + 1 on.  Every
-// lane of the wave steps through the same widths; `valid` lanes merge their
-// maxima into the slots.
-template <int K, int KF>
-__device__ __forceinline__ void eval_starts(const float *__restrict__ Pl, uint32_t st, bool valid,
-                                            uint32_t wfirst, const_fptr thr, uint32_t zmax,
-                                            uint32_t zc, unsigned long long *slot_row,
-                                            uint32_t bin0) {
+// Exact evaluation of width block b (widths bK+1 .. bK+K) for starts
+// k0 .. k0+KS-1 of lane L of the tile (bins LK+k0 ..): one work unit of the
+// cooperative pass.  The state of the canonical order after width bK is
+// rebuilt from the group sums: the window of start s has crossed b group
+// boundaries, so hb = H_s + Sg[L+1] + ... + Sg[L+b-1], with H_s the sum of
+// bins LK+s .. LK+K-1, and t holds the first s bins of group L+b.  A window
+// that already reaches past the spectrum's end (tile bin `rem`) is -inf, as
+// the dense route's running sum would be.
+template <int K>
+__device__ __forceinline__ void eval_unit(const float *__restrict__ Pl,
+                                          const float *__restrict__ Sg,
+                                          const float *__restrict__ Tl, uint32_t L, uint32_t b,
+                                          int k0, uint32_t rem, uint32_t zmax,
+                                          unsigned long long *slot_row, uint32_t bin0) {
   constexpr int PITCH = pitch_of<K>();
-  float s[KF], q[2 * KF];
+  constexpr int KS = ks_of<K>();
+  float hb[KS], t[KS], q[KS + K - 1];
+  if (b == 0) {
 #pragma unroll
-  for (int k = 0; k < KF; ++k) s[k] = 0.f;
-  {
-    const uint32_t a = paddr<K>(st);  // KF | st and KF | K: the group stays in one column
+    for (int k = 0; k < KS; ++k) hb[k] = t[k] = 0.f;
+  } else {
+    const float *po = Pl + (L >> 6) * (K * PITCH) + (L & 63);
 #pragma unroll
-    for (int v = 0; v < KF; ++v) q[v] = Pl[a + v * PITCH];
+    for (int k = KS - 1; k >= 0; --k) {
+      // H_s adds bins s .. K-1 in increasing order from zero
+      float a = po[(k0 + k) * PITCH];
+#pragma unroll
+      for (int v = k0 + k + 1; v < K; ++v) a += po[v * PITCH];
+      hb[k] = a;
+    }
+    for (uint32_t j = 1; j < b; ++j) {
+      const float gs = Sg[L + j];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) hb[k] += gs;
+    }
+    // t: the first s bins of group L+b, s = k0 + k
+    const uint32_t Lg = L + b;
+    const float *pg = Pl + (Lg >> 6) * (K * PITCH) + (Lg & 63);
+    float pre = 0.f;
+#pragma unroll
+    for (int v = 0; v < k0; ++v) pre += pg[v * PITCH];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      t[k] = pre;
+      if (k + 1 < KS) pre += pg[(k0 + k) * PITCH];
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+      if (L * K + k0 + k + b * K > rem) hb[k] = -INFINITY;
   }
-  for (uint32_t wb = 0; wb < zc; wb += KF) {
-    {
-      const uint32_t a = paddr<K>(st + wb + KF);
+  load_window<K>(Pl, L, b * K, k0, q);
+  width_block<K>(q, hb, t, k0, Tl + b * K, b * K, zmax, slot_row, bin0);
+}
+
+// Exclusive scan of the per-tile candidate counts by the workgroup that
+// finished last.  Each tile publishes its count as one relaxed 64-bit word
+// (generation << 32 | count); a word of an earlier launch is waited for
+// rather than fenced, so no tile pays for a device-wide release.  Thread t
+// sums a contiguous run of tiles, the run totals are scanned across the
+// workgroup, and each thread writes its run's prefixes.  Also records the
+// total and the staging overflow, and re-arms the pool head and the
+// finished-tile counter for the next launch.
+constexpr uint32_t kWordSpin = 1u << 22;  // polls per word before giving up
+
+__device__ __forceinline__ uint32_t tile_count_of(const BankParams &p, uint64_t i, bool &lost) {
+  unsigned long long v = 0;
+  for (uint32_t k = 0; k < kWordSpin; ++k) {
+    v = __hip_atomic_load(p.tile_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(v >> 32) == p.gen) return (uint32_t)v;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  lost = true;  // reported through the overflow flag
+  return 0u;
+}
+
+__device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uint32_t *wave_sum,
+                           uint32_t *lost_any) {
+  const uint32_t lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  const uint64_t T = p.total_tiles;
+  const uint64_t per = (T + nthr - 1) / nthr;
+  const uint64_t lo = min((uint64_t)tid * per, T), hi = min(lo + per, T);
+  bool lost = false;
+  uint32_t mine = 0;
+  for (uint64_t i = lo; i < hi; ++i) mine += tile_count_of(p, i, lost);
+  if (lost) atomicOr(lost_any, 1u);
+  uint32_t incl = mine;
 #pragma unroll
-      for (int v = 0; v < KF; ++v) q[KF + v] = Pl[a + v * PITCH];
-    }
-#pragma unroll
-    for (int u = 0; u < KF; ++u) {
-#pragma unroll
-      for (int k = 0; k < KF; ++k) s[k] += q[k + u];  // width wb+u+1
-      const uint32_t w = wb + u + 1;
-      const float Tw = thr[wb + u];
-      float m = s[0];
-#pragma unroll
-      for (int k = 1; k < KF; ++k) m = fmaxf(m, s[k]);
-      if (valid && w > wfirst && m >= Tw && w <= zmax) {
-        uint32_t kk = KF - 1;
-#pragma unroll
-        for (int k = KF - 2; k >= 0; --k) kk = (s[k] == m) ? (uint32_t)k : kk;
-        const unsigned long long key =
-            ((unsigned long long)ord_f32(m) << 32) | (0xFFFFFFFFu - (bin0 + kk));
-        atomicMax(&slot_row[w - 1], key);
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < KF; ++v) q[v] = q[KF + v];
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += v;
+  }
+  if (lane == 63) wave_sum[wave] = incl;
+  __syncthreads();
+  uint32_t run = 0, tot = 0;
+  for (uint32_t v = 0; v < nw; ++v) {
+    run += v < wave ? wave_sum[v] : 0u;
+    tot += wave_sum[v];
+  }
+  run += incl - mine;
+  for (uint64_t i = lo; i < hi; ++i) {
+    p.tile_prefix[i] = run;
+    run += (uint32_t)__hip_atomic_load(p.tile_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    p.tile_prefix[T] = tot;
+    *p.total = tot;
+    if (p.total2) *p.total2 = tot;
+    *p.overflow = *lost_any ? 2u : (tot > p.pool_cap ? 1u : 0u);
+    __hip_atomic_store(p.pool_head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -453,11 +575,11 @@ template <int EPL>
 constexpr int threads_for() {
   return EPL >= 64 ? 256 : kMaxThreads;  // 4096-bin blocks need the whole register file
 }
-// Waves per SIMD the register allocation must allow: 4 lets two 8-wave
+// Waves per SIMD the register allocation must allow: 6 lets three 8-wave
 // workgroups share a CU.
 template <int EPL>
 constexpr int waves_per_eu_for() {
-  return EPL >= 64 ? 1 : 4;
+  return EPL >= 64 ? 1 : 6;
 }
 
 template <int K, int EPL>
@@ -468,6 +590,8 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
   __shared__ uint32_t tile_base;
   __shared__ uint32_t any_dense;
   __shared__ uint32_t n_items;
+  __shared__ uint32_t is_last;
+  __shared__ uint32_t lost_any;
   constexpr uint32_t SEG = 64 * K;
   constexpr uint32_t B = 64 * EPL;
   constexpr int PITCH = pitch_of<K>();
@@ -486,13 +610,16 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
   uint32_t *items = reinterpret_cast<uint32_t *>(Sg + p.nseg_lds * 64);  // T / K entries
   float *Pl = reinterpret_cast<float *>(items + T / K);
 
-  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-  // contiguous run of tiles so the halo a tile shares with its neighbour is
-  // read through the same L2.
+  // One tile per workgroup.  Workgroups are dealt round-robin to the 8
+  // XCDs; give each XCD a contiguous run of tiles so the halo a tile shares
+  // with its neighbour is read through the same L2.
   uint64_t first_tile = blockIdx.x;
   if ((gridDim.x & 7) == 0) first_tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
 
-  for (uint64_t tg = first_tile; tg < p.total_tiles; tg += gridDim.x) {
+  if (first_tile >= p.total_tiles) return;
+  {
+    const uint64_t tg = first_tile;
+    uint32_t ticket = 0;  // thread 0: this tile's place in the order tiles start
     int sidx = 0;
     if (p.nspec > 1) {
       int lo = 0, hi = p.nspec - 1;
@@ -517,23 +644,29 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
     // --- set-up and power --------------------------------------------------
     // the wave's first block is requested before anything else so that its
     // memory latency overlaps the set-up
+    {
+    const uint32_t tid = fresh_tid(), lane = tid & 63, wave = tid >> 6;
     BlockData<EPL> bd;
     const bool have = !p.from_power && bfirst + wave <= blast;
     if (have) load_block<EPL>(d.x, n, bfirst + wave, lane, bd);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       any_dense = 0u;
       n_items = 0u;
+      // the tile that starts last scans the per-tile counts once every tile
+      // has published its count; taking the ticket now hides its latency
+      // behind the spectrum loads
+      if (p.mode == kModeSearch) ticket = atomicAdd(p.done, 1u);
     }
-    for (uint32_t i = threadIdx.x; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
-    for (uint32_t i = threadIdx.x; i < zc; i += nthr) Tl[i] = d.thr[i];
-    if (threadIdx.x < 4) {
+    for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
+    for (uint32_t i = tid; i < zc; i += nthr) Tl[i] = d.thr[i];
+    if (tid < 4) {
       constexpr int S = K < kSub ? K : kSub;
       float m = INFINITY;
-      if (threadIdx.x * S < (uint32_t)K)
-        for (int u = 0; u < S; ++u) m = fminf(m, d.thr[threadIdx.x * S + u]);
-      Tb1[threadIdx.x] = m * kBoundSlack;
+      if (tid * S < (uint32_t)K)
+        for (int u = 0; u < S; ++u) m = fminf(m, d.thr[tid * S + u]);
+      Tb1[tid] = m * kBoundSlack;
     }
-    for (uint32_t i = threadIdx.x; i < nblk; i += nthr) {
+    for (uint32_t i = tid; i < nblk; i += nthr) {
       float m = d.thr[i * K];
       for (int u = 1; u < K; ++u) m = fminf(m, d.thr[i * K + u]);
       Tb[i] = m * kBoundSlack;
@@ -541,20 +674,20 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
     // bins past the spectrum's end are -inf (no window may contain them);
     // halo bins beyond what any width <= zmax reads are 0 (read only by the
     // unrecorded widths zmax+1..zc and by the pruning bound)
-    for (uint32_t i = need + threadIdx.x; i < span; i += nthr)
+    for (uint32_t i = need + tid; i < span; i += nthr)
       Pl[paddr<K>(i)] = i < rem ? 0.f : -INFINITY;
     if (p.from_power) {
       const float *pw = reinterpret_cast<const float *>(d.x);
-      for (uint32_t i = threadIdx.x; i < need; i += nthr) Pl[paddr<K>(i)] = pw[t0 + i];
+      for (uint32_t i = tid; i < need; i += nthr) Pl[paddr<K>(i)] = pw[t0 + i];
     } else if (have) {
       const bool dbg = p.mode == kModeTables;
       float *po = dbg ? p.P_out : nullptr;
       float *so = dbg ? p.stats_out : nullptr;
-      normalise_block<K, EPL>(bd, bfirst + wave, t0, need, T, Pl, lane, po, so);
-      for (uint32_t b = bfirst + wave + nw; b <= blast; b += nw) {
-        load_block<EPL>(d.x, n, b, lane, bd);
+      for (uint32_t b = bfirst + wave; b <= blast; b += nw) {
+        if (b != bfirst + wave) load_block<EPL>(d.x, n, b, lane, bd);
         normalise_block<K, EPL>(bd, b, t0, need, T, Pl, lane, po, so);
       }
+    }
     }
     __syncthreads();
 
@@ -562,9 +695,10 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
     const bool prune = !p.dense && p.mode != kModeTables;
     const bool clamp = rem < span;
     if (prune) {
+      const uint32_t tid = fresh_tid();
       // K-bin group sums of the whole span (inputs of the pruning bound)
       const uint32_t ngroups = span / K;
-      for (uint32_t j = threadIdx.x; j < ngroups; j += nthr) {
+      for (uint32_t j = tid; j < ngroups; j += nthr) {
         const float *cp = Pl + (j >> 6) * (K * PITCH) + (j & 63);
         float a = 0.f;
         if (clamp) {
@@ -581,6 +715,8 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
     const uint32_t nseg_tile = T / SEG;
     const const_fptr thr = uniform_const(d.thr);
     if (prune) {
+      {
+      const uint32_t tid = fresh_tid(), lane = tid & 63, wave = tid >> 6;
       // each lane's first width block that might reach a threshold; the
       // flagged lanes become work items of a cooperative exact pass
       for (uint32_t g = wave; g < nseg_tile; g += nw) {
@@ -596,92 +732,106 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
             items[base + __popcll(mask & ((1ull << lane) - 1ull))] = ((g * 64 + lane) << 12) | fl;
         }
       }
+      }
       __syncthreads();
-      constexpr int KF = K < 4 ? K : 4;
-      const uint32_t nsub = n_items * (K / KF);
-      if (threadIdx.x == 0 && nsub) any_dense = 1u;
-      for (uint32_t r = 0; r < nsub; r += nthr) {
-        const uint32_t j = r + threadIdx.x;
-        const bool valid = j < nsub;
-        const uint32_t it = valid ? items[j / (K / KF)] : 0u;
-        const uint32_t st = (it >> 12) * K + (j % (K / KF)) * KF;  // tile-relative first start
-        const uint32_t wfirst = (it & 0xFFFu) * K;
-        eval_starts<K, KF>(Pl, valid ? st : 0u, valid, wfirst, thr, zmax, zc,
-                           slots + (size_t)((valid ? st : 0u) / C) * zmax, t0 + st);
+      // work units (flagged lane, width block), lane-major, so that the lanes
+      // of a wave share lanes' chunks but not widths: their slot merges
+      // rarely collide
+      const uint32_t tid = fresh_tid();
+      const uint32_t nb = (zmax + K - 1) / K;
+      constexpr uint32_t NH = K / ks_of<K>();  // start groups per lane
+      const uint32_t nunits = n_items * nb * NH;
+      if (tid == 0 && nunits) any_dense = 1u;
+      for (uint32_t r = 0; r < nunits; r += nthr) {
+        const uint32_t j = r + tid;
+        const uint32_t jj = j / NH;
+        const uint32_t it = j < nunits ? items[jj / nb] : 0u;
+        const uint32_t b = j < nunits ? jj % nb : 0u;
+        if (j < nunits && b >= (it & 0xFFFu)) {
+          const uint32_t L = it >> 12;
+          unsigned long long *row = slots + (size_t)((L * K) / C) * zmax;
+          if (NH == 1 || j % NH == 0)
+            eval_unit<K>(Pl, Sg, Tl, L, b, 0, rem, zmax, row, t0 + L * K);
+          else
+            eval_unit<K>(Pl, Sg, Tl, L, b, ks_of<K>(), rem, zmax, row, t0 + L * K);
+        }
       }
     } else {
+      const uint32_t tid = fresh_tid(), lane = tid & 63, wave = tid >> 6;
       for (uint32_t g = wave; g < nseg_tile; g += nw) {
         const uint32_t seg0 = g * SEG;
         if (seg0 >= rem) break;
         any_dense = 1u;
-        bank_dense<K>(Pl, g, lane, thr, zmax, zc, 0u, slots + (size_t)(seg0 / C) * zmax,
+        bank_dense<K>(Pl, g, lane, thr, zmax, zc, slots + (size_t)(seg0 / C) * zmax,
                       t0 + seg0 + lane * K);
       }
     }
     __syncthreads();
 
+    {
+    const uint32_t tid = fresh_tid(), lane = tid & 63, wave = tid >> 6;
     // --- extraction ----------------------------------------------------------
     const uint32_t chunk0 = t0 / C;
     const uint32_t nch = min(chunks_per_tile, d.nchunks - chunk0);
     const uint32_t nsl = nch * zmax;
-    if (p.mode == kModeSearch && !any_dense) {
-      // no wave evaluated a width block: no slot can hold a maximum
-      if (threadIdx.x == 0) {
-        p.tile_count[tg] = 0u;
-        p.tile_pos[tg] = 0u;
-      }
-    } else if (p.mode == kModeSearch) {
+    if (p.mode == kModeSearch) {
       // stage the tile's maxima in slot order, i.e. (chunk, width) order:
-      // count, reserve one run of the pool, then write with ordered ranks
+      // thread t takes a contiguous run of slots; ranks come from a scan of
+      // the run counts, one atomic reserves the tile's run of the pool
+      const uint32_t per = any_dense ? (nsl + nthr - 1) / nthr : 0u;
+      const uint32_t lo = min(tid * per, nsl), hi = min(lo + per, nsl);
       uint32_t mine = 0;
-      for (uint32_t i = threadIdx.x; i < nsl; i += nthr) mine += slots[i] != 0ull ? 1u : 0u;
-      for (int o = 32; o >= 1; o >>= 1) mine += __shfl_xor(mine, o, 64);
-      if (lane == 0) wave_sum[wave] = mine;
+      for (uint32_t i = lo; i < hi; ++i) mine += slots[i] != 0ull ? 1u : 0u;
+      uint32_t incl = mine;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o) incl += v;
+      }
+      if (lane == 63) wave_sum[wave] = incl;
       __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (uint32_t v = 0; v < nw; ++v) tot += wave_sum[v];
-        const uint32_t base = tot ? atomicAdd(p.pool_head, tot) : 0u;
-        p.tile_count[tg] = tot;
-        p.tile_pos[tg] = base;
-        tile_base = base;
+      uint32_t before = 0, tot = 0;
+      for (uint32_t v = 0; v < nw; ++v) {
+        before += v < wave ? wave_sum[v] : 0u;
+        tot += wave_sum[v];
+      }
+      if (tid == 0) {
+        tile_base = tot ? atomicAdd(p.pool_head, tot) : 0u;
+        // the pool reservation has been performed before the count is
+        // published, so the scanning tile may re-arm the pool head
+        __builtin_amdgcn_s_waitcnt(0);
+        __hip_atomic_store(p.tile_word + tg, ((unsigned long long)p.gen << 32) | tot,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = ticket == (uint32_t)(p.total_tiles - 1) ? 1u : 0u;
+        lost_any = 0u;
       }
       __syncthreads();
-      uint32_t run = tile_base;
-      for (uint32_t r = 0; r < nsl; r += nthr) {
-        const uint32_t i = r + threadIdx.x;
-        const unsigned long long key = i < nsl ? slots[i] : 0ull;
-        const bool valid = key != 0ull;
-        const unsigned long long mask = __ballot(valid);
-        if (lane == 0) wave_sum[wave] = (uint32_t)__popcll(mask);
-        __syncthreads();
-        uint32_t before = 0, all = 0;
-        for (uint32_t v = 0; v < nw; ++v) {
-          before += v < wave ? wave_sum[v] : 0u;
-          all += wave_sum[v];
+      uint32_t rank = before + incl - mine;
+      for (uint32_t i = lo; i < hi; ++i) {
+        const unsigned long long key = slots[i];
+        if (key == 0ull) continue;
+        const uint32_t pos = tile_base + rank;
+        if (pos < p.pool_cap) {
+          const uint32_t cl = i / zmax, w = i - cl * zmax + 1;
+          StageEntry e;
+          e.tile = (uint32_t)tg;
+          e.bin = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+          e.power = unord_f32((uint32_t)(key >> 32));
+          e.rank_width = (rank << kWidthBits) | (w - 1);
+          p.pool[pos] = e;
         }
-        if (valid) {
-          const uint32_t pos = run + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-          if (pos < p.pool_cap) {
-            const uint32_t cl = i / zmax, w = i - cl * zmax + 1;
-            StageEntry e;
-            e.chunk = chunk0 + cl;
-            e.bin = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
-            e.power = unord_f32((uint32_t)(key >> 32));
-            e.width = w;
-            p.pool[pos] = e;
-          }
-        }
-        run += all;
-        __syncthreads();
+        ++rank;
       }
+      // the last tile to finish scans the per-tile counts
+      if (is_last) scan_tiles(p, tid, nthr, wave_sum, &lost_any);
     } else {
-      for (uint32_t i = threadIdx.x; i < nsl; i += nthr) {
+      for (uint32_t i = tid; i < nsl; i += nthr) {
         const unsigned long long key = slots[i];
         const size_t o = (size_t)chunk0 * zmax + i;
         p.M[o] = key ? unord_f32((uint32_t)(key >> 32)) : -INFINITY;
         p.I[o] = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : 0xFFFFFFFFu;
       }
+    }
     }
     __syncthreads();
   }
@@ -723,7 +873,8 @@ static uint64_t gcd_u(uint64_t a, uint64_t b) {
 }
 static uint64_t lcm_u(uint64_t a, uint64_t b) { return a / gcd_u(a, b) * b; }
 
-constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsBudget = 64 * 1024;     // per workgroup
+constexpr size_t kLdsPreferred = 53 * 1024;  // three workgroups share a CU's 160 KiB
 constexpr uint32_t kMaxWaves = 8;
 
 bool choose_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, uint64_t n_hint, Geometry *g) {
@@ -738,11 +889,14 @@ bool choose_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, uint64_t n_hint,
   const uint32_t wmax = B == 4096 ? 4u : kMaxWaves;
   uint32_t nseg = 0, zcp = 0;
   // largest tile (a multiple of L0) whose blocks plus halo blocks give every
-  // wave one block, that fits in LDS and leaves enough tiles to fill the GPU
+  // wave one block, that leaves room for three workgroups per CU (the
+  // smallest tile may use up to the per-workgroup budget) and enough tiles
+  // to fill the GPU
   uint64_t T = 0;
   for (uint64_t t = L0; t <= (uint64_t)kMaxTile; t += L0) {
     if (t / B + halo > wmax && t > L0) break;
-    if (lds_need(K, (uint32_t)t, C, zmax_max, &nseg, &zcp) > kLdsBudget) break;
+    const size_t lds = lds_need(K, (uint32_t)t, C, zmax_max, &nseg, &zcp);
+    if (lds > kLdsBudget || (lds > kLdsPreferred && t > L0)) break;
     if (t > L0 && n_hint / t < 256) break;
     T = t;
   }

@@ -30,13 +30,15 @@ struct SpecDesc {
 };
 
 // A staged candidate.  Each tile writes its own in (chunk, width) order to a
-// contiguous run of the staging pool.
+// contiguous run of the staging pool; its place in the canonical output is
+// the tile's exclusive prefix plus its rank within the tile.
 struct StageEntry {
-  uint32_t chunk;  // chunk index within the spectrum
-  uint32_t bin;    // window start
-  float power;     // boxcar power
-  uint32_t width;  // 1..zmax
+  uint32_t tile;        // global tile index
+  uint32_t bin;         // window start
+  float power;          // boxcar power
+  uint32_t rank_width;  // rank within the tile << 12 | (width - 1)
 };
+constexpr uint32_t kWidthBits = 12;  // zmax <= 4096
 
 enum BankMode : int {
   kModeSearch = 0,   // stage (chunk, width) maxima that reach the threshold
@@ -58,11 +60,18 @@ struct BankParams {
   int mode;                // BankMode
   int from_power;          // x holds float power; skip normalisation
   int dense;               // 1: skip the pruning bound (every width block evaluated)
-  StageEntry *pool;        // search mode: staging pool
+  // search mode: candidate staging and the scan of the per-tile counts,
+  // which the workgroup that finishes last performs
+  StageEntry *pool;        // staging pool
   uint32_t pool_cap;       // entries in the pool
-  uint32_t *pool_head;     // next free pool entry (reset to 0 by the scan kernel)
-  uint32_t *tile_count;    // per tile: candidates it staged
-  uint32_t *tile_pos;      // per tile: pool offset of its first candidate
+  uint32_t *pool_head;     // next free pool entry (re-armed to 0 by the scan)
+  uint32_t *done;          // tiles finished (re-armed to 0 by the scan)
+  unsigned long long *tile_word;  // per tile: gen << 32 | candidates it staged
+  uint32_t gen;            // this launch's generation (never 0; words start at 0)
+  uint32_t *tile_prefix;   // per tile: exclusive prefix of the counts; [total_tiles] = total
+  unsigned long long *total;   // candidate count (device)
+  unsigned long long *total2;  // optional second destination (the caller's)
+  uint32_t *overflow;      // 1: the pool was too small; 2: a tile's count never arrived
   float *M;                // tables mode: nchunks x zmax (spectrum 0 only)
   uint32_t *I;
   float *P_out;            // tables mode, optional: normalised power
@@ -105,30 +114,16 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
                              uint32_t zc_max, double sigma, int width_search, int debug,
                              hipStream_t stream);
 
-// Exclusive scan of the per-tile candidate counts (one workgroup), the total
-// count, the staging-overflow flag, and the reset of the pool head.
-struct ScanParams {
-  const uint32_t *tile_count;
-  uint32_t *tile_prefix;           // total_tiles + 1 entries
-  uint64_t total_tiles;
-  uint32_t *pool_head;
-  uint32_t pool_cap;
-  unsigned long long *total;       // device
-  unsigned long long *total2;      // optional second device destination (caller's)
-  uint32_t *overflow;              // set to 1 when the pool was too small
-};
-hipError_t launch_scan(const ScanParams &p, hipStream_t stream);
-
-// Candidate f of the canonical order goes to out[f] (f < capacity), with its
-// FP64 significance.
+// Candidate f of the staging pool goes to out[tile_prefix[tile] + rank]
+// (when that is below capacity), with its FP64 significance.
 struct EmitParams {
   const SpecDesc *descs;           // device table, or nullptr for one spectrum
   int nspec;
   const StageEntry *pool;
   uint32_t pool_cap;
   const uint32_t *tile_prefix;
-  const uint32_t *tile_pos;
-  uint64_t total_tiles;
+  const unsigned long long *total;
+  uint32_t chunk;
   pulscan_candidate *out;
   uint64_t capacity;
 };

@@ -19,8 +19,9 @@ __device__ double log_sf_chi2_even(double x, uint32_t w) {
   const uint32_t kp = (y >= (double)(w - 1)) ? w - 1 : (uint32_t)floor(y);
   const double log_peak = (double)kp * log(y) - lgamma((double)kp + 1.0);
   double acc = 1.0, r = 1.0;
+  const double iy = 1.0 / y;
   for (uint32_t k = kp; k >= 1; --k) {  // terms below the peak shrink by k / y
-    r *= (double)k / y;
+    r *= (double)k * iy;
     acc += r;
     if (r < 1e-18 * acc) break;
   }
@@ -46,19 +47,32 @@ __device__ double log_norm_sf(double s) {
   return log(0.5 * erfc(s * M_SQRT1_2));
 }
 
-// d/ds log Phi_c(s) = -phi(s) / Phi_c(s).
-__device__ double dlog_norm_sf(double s) {
-  if (s > 0.0) return -M_SQRT2 / (sqrt(M_PI) * erfcx(s * M_SQRT1_2));
-  return -exp(-0.5 * s * s - 0.5 * log(2.0 * M_PI) - log_norm_sf(s));
+// log Phi_c(s) and its derivative -phi(s) / Phi_c(s) together (one erfcx).
+__device__ void log_norm_sf_d(double s, double &f, double &df) {
+  if (s > 0.0) {
+    const double ex = erfcx(s * M_SQRT1_2);
+    f = -0.5 * s * s + log(0.5 * ex);
+    df = -M_SQRT2 / (sqrt(M_PI) * ex);
+  } else {
+    f = log(0.5 * erfc(s * M_SQRT1_2));
+    df = -exp(-0.5 * s * s - 0.5 * log(2.0 * M_PI) - f);
+  }
 }
 
 // The s with log Phi_c(s) = L (L < 0); -inf for L >= 0.  Newton's method on a
-// concave, decreasing function converges from either side of the root.
+// concave, decreasing function converges from either side of the root; the
+// start solves the tail's leading terms, -s^2/2 - ln(s sqrt(2 pi)) = L.
 __device__ double sigma_from_logp(double L) {
   if (!(L < 0.0)) return -INFINITY;
-  double s = (L < -1.0) ? sqrt(-2.0 * L) : 0.0;
+  double s = 0.0;
+  if (L < -1.0) {
+    s = sqrt(-2.0 * L);
+    s = sqrt(fmax(-2.0 * L - 2.0 * log(s * 2.5066282746310002), 1.0));
+  }
   for (int it = 0; it < 200; ++it) {
-    const double step = (log_norm_sf(s) - L) / dlog_norm_sf(s);
+    double f, df;
+    log_norm_sf_d(s, f, df);
+    const double step = (f - L) / df;
     s -= step;
     if (fabs(step) <= 1e-14 * fmax(1.0, fabs(s))) break;
   }
@@ -117,79 +131,25 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
 }
 
 // ---------------------------------------------------------------------------
-// Scan of the per-tile counts: one workgroup.  Thread t sums a contiguous
-// run of tiles, the run totals are scanned in LDS, and each thread writes the
-// prefixes of its run.
-
-constexpr int kScanThreads = 1024;
-
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(ScanParams p) {
-  __shared__ uint32_t part[kScanThreads];
-  const uint64_t T = p.total_tiles;
-  const uint64_t per = (T + kScanThreads - 1) / kScanThreads;
-  const uint64_t lo = (uint64_t)threadIdx.x * per;
-  const uint64_t hi = lo + per < T ? lo + per : T;
-  uint32_t sum = 0;
-  for (uint64_t t = lo; t < hi; ++t) sum += p.tile_count[t];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the run totals
-  for (int o = 1; o < kScanThreads; o <<= 1) {
-    const uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (uint64_t t = lo; t < hi; ++t) {
-    p.tile_prefix[t] = run;
-    run += p.tile_count[t];
-  }
-  if (threadIdx.x == kScanThreads - 1) {
-    const uint32_t total = part[kScanThreads - 1];
-    p.tile_prefix[T] = total;
-    if (p.total) *p.total = total;
-    if (p.total2) *p.total2 = total;
-    *p.overflow = *p.pool_head > p.pool_cap ? 1u : 0u;
-    *p.pool_head = 0u;
-  }
-}
-
-hipError_t launch_scan(const ScanParams &p, hipStream_t stream) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, p);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Emit: candidate f of the canonical order (tile order, then the tile's own
-// (chunk, width) order) is found by binary search over the tile prefixes.
+// Emit: pool entry f (tile, rank) goes to its canonical place, the tile's
+// exclusive prefix plus its rank, with its Gaussian-equivalent sigma.
 
 constexpr int kEmitThreads = 256;
 
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDesc single) {
-  const uint64_t T = p.total_tiles;
-  const uint64_t total = p.tile_prefix[T];
-  const uint64_t lim = total < p.capacity ? total : p.capacity;
+  const unsigned long long total = *p.total;
+  const uint64_t lim = total < p.pool_cap ? total : p.pool_cap;
   const uint64_t stride = (uint64_t)gridDim.x * kEmitThreads;
   for (uint64_t f = (uint64_t)blockIdx.x * kEmitThreads + threadIdx.x; f < lim; f += stride) {
-    // largest t with tile_prefix[t] <= f (that tile holds candidate f)
-    uint64_t lo = 0, hi = T - 1;
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi + 1) >> 1;
-      if (p.tile_prefix[mid] <= f)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const uint64_t t = lo;
-    const uint64_t idx = (uint64_t)p.tile_pos[t] + (f - p.tile_prefix[t]);
-    if (idx >= p.pool_cap) continue;  // lost to a staging overflow (reported)
+    const StageEntry e = p.pool[f];
+    const uint64_t dest = (uint64_t)p.tile_prefix[e.tile] + (e.rank_width >> kWidthBits);
+    if (dest >= p.capacity) continue;
     int s = 0;
     if (p.nspec > 1) {
       int a = 0, b = p.nspec - 1;
       while (a < b) {
         const int mid = (a + b + 1) >> 1;
-        if (p.descs[mid].tile_begin <= t)
+        if (p.descs[mid].tile_begin <= e.tile)
           a = mid;
         else
           b = mid - 1;
@@ -197,16 +157,16 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
       s = a;
     }
     const double ntrials = p.nspec > 1 ? p.descs[s].ntrials : single.ntrials;
-    const StageEntry e = p.pool[idx];
-    const double lp = log_sf_chi2_even((double)e.power, e.width) + log(ntrials);
+    const uint32_t w = (e.rank_width & ((1u << kWidthBits) - 1u)) + 1u;
+    const double lp = log_sf_chi2_even((double)e.power, w) + log(ntrials);
     pulscan_candidate c;
     c.spectrum = (uint32_t)s;
     c.bin = e.bin;
-    c.width = e.width;
+    c.width = w;
     c.power = e.power;
     c.sigma = (float)sigma_from_logp(lp < 0.0 ? lp : 0.0);
-    c.chunk = e.chunk;
-    p.out[f] = c;
+    c.chunk = e.bin / p.chunk;
+    p.out[dest] = c;
   }
 }
 
