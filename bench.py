@@ -89,7 +89,7 @@ def main():
     d = torch.from_numpy(x).to("cuda:0")
     stream = torch.cuda.current_stream()
     cap = ((n + C - 1) // C) * Z
-    out_buf = torch.empty(cap * 24, dtype=torch.uint8, device="cuda:0")
+    out_buf = torch.empty(cap * pk.CANDIDATE_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
 
     ref, ref_count = ctx.pulscan_search_ex(d, Z, C, sigma)

@@ -23,8 +23,15 @@
  *     0 normalises to 0.  The MAD scale is 1 / Phi^-1(3/4).
  *   - ntrials (the Bonferroni factor) defaults to nbins * (number of
  *     searched widths).
- *   - Candidates come out in canonical order: ascending (spectrum, chunk,
- *     width).  Results are deterministic.
+ *   - Harmonic summing (opts.numharm = Hmax > 1, section 2.3 and the
+ *     appendix algorithm "Harmonic Sum Decimation"): stage H searches
+ *     S_H[r] = sum_{h=1..H} (P[h r] + ... + P[h r + h - 1]) over its
+ *     floor(nbins / H) bins exactly as the power itself (chunks, windows,
+ *     maxima), with H(H+1) w degrees of freedom for a width-w boxcar and, by
+ *     default, ntrials = floor(nbins / H) * searched widths.  Stage 1 is the
+ *     power.
+ *   - Candidates come out in canonical order: ascending (spectrum, harmonic
+ *     stage, chunk, width).  Results are deterministic.
  *   - Inputs must be finite; NaN or infinite amplitudes give undefined
  *     candidates (no crash).
  *
@@ -74,13 +81,18 @@ typedef struct {
 
 /* One candidate: a per-chunk maximum whose significance reached the threshold. */
 typedef struct {
-  uint32_t spectrum; /* index in the batch; 0 for single-spectrum calls          */
-  uint32_t bin;      /* left edge of the window, 0-based (the paper's r-bin)     */
-  uint32_t width;    /* boxcar width 1..zmax; the paper's z-bin is width - 1     */
-  float power;       /* boxcar power of the window, FP32                         */
-  float sigma;       /* Bonferroni-corrected Gaussian-equivalent significance    */
-  uint32_t chunk;    /* chunk index, bin / chunk                                 */
-} pulscan_candidate; /* 24 bytes */
+  uint32_t spectrum;  /* index in the batch; 0 for single-spectrum calls          */
+  uint32_t bin;       /* left edge of the window, 0-based (the paper's r-bin), in
+                         the searched series (harmonic stage H: the fundamental's
+                         r-bin); with opts.rblock > 0, the r-block index
+                         bin / rblock instead (section 2.4)                       */
+  uint32_t width;     /* boxcar width 1..zmax; the paper's z-bin is width - 1     */
+  float power;        /* boxcar power of the window, FP32                         */
+  float sigma;        /* Bonferroni-corrected Gaussian-equivalent significance    */
+  uint32_t chunk;     /* chunk index, bin / chunk (of the exact bin)              */
+  uint32_t harmonics; /* harmonic stage H (1: the power itself), section 2.3      */
+  uint32_t reserved;
+} pulscan_candidate;  /* 32 bytes */
 
 /* Caller-owned candidate buffer. */
 typedef struct {
@@ -113,7 +125,13 @@ typedef struct {
   int32_t dense;        /* 0 (default): skip width blocks that a running upper bound
                            proves cannot reach their threshold (exact: the same
                            candidates).  1: evaluate every width block            */
-  int32_t reserved;
+  int32_t numharm;      /* harmonic stages searched, 1..16; 0 or 1 = the power only */
+  int32_t best_per_chunk; /* 1: of the candidates of one (spectrum, stage, chunk),
+                           keep only the one of highest sigma (the first in
+                           canonical order on ties); count is then the number
+                           of chunks kept                                          */
+  int32_t rblock;       /* > 0: candidates report the r-block index bin / rblock in
+                           place of the bin (section 2.4); 0 = exact bins         */
 } pulscan_opts;
 
 typedef struct pulscan_ctx pulscan_ctx;
@@ -122,7 +140,8 @@ typedef struct pulscan_ctx pulscan_ctx;
 const char *pulscan_strerror(int status);
 
 /* Default options: MoM normalisation, block = chunk, default ntrials, all widths,
- * synchronous, the null stream. */
+ * synchronous, the null stream, pruned bank, no harmonic summing, every
+ * candidate, exact bins. */
 void pulscan_opts_default(pulscan_opts *opts);
 
 /* Create a context on HIP device `device` (it becomes current for the calls

@@ -35,12 +35,12 @@ def build(force: bool = True) -> str:
 
 class _Cand(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int64), ("bin", ctypes.c_int64), ("width", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("power", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("harm", ctypes.c_int32), ("power", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("logp", ctypes.c_double)]
 
 
 CAND_DTYPE = np.dtype([("chunk", np.int64), ("bin", np.int64), ("width", np.int32),
-                       ("pad", np.int32), ("power", np.float64), ("sigma", np.float64),
+                       ("harm", np.int32), ("power", np.float64), ("sigma", np.float64),
                        ("logp", np.float64)])
 assert CAND_DTYPE.itemsize == ctypes.sizeof(_Cand)
 
@@ -86,6 +86,13 @@ def lib():
         L.oracle_search.argtypes = [fp, i64, ctypes.c_int, i64, ctypes.c_double, i64, ctypes.c_int,
                                     ctypes.c_double, ctypes.c_int, i64, ctypes.POINTER(_Cand), dp,
                                     ctypes.POINTER(ctypes.c_int64), dp]
+        L.oracle_search_harm.restype = i64
+        L.oracle_search_harm.argtypes = [fp, i64, ctypes.c_int, i64, ctypes.c_double, i64,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         i64, ctypes.POINTER(_Cand), dp,
+                                         ctypes.POINTER(ctypes.c_int64), dp]
+        L.oracle_harmonic_sum.restype = i64
+        L.oracle_harmonic_sum.argtypes = [dp, i64, ctypes.c_int, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -169,6 +176,15 @@ def chunk_maxima(P, zmax: int, chunk: int):
     return M, I
 
 
+def harmonic_sum(P, H: int):
+    """Stage-H harmonic sum S_H (floor(n / H) values) of a power series."""
+    P = _as_f64(P)
+    S = np.empty(max(P.size // max(H, 1), 0))
+    m = lib().oracle_harmonic_sum(_dptr(P), P.size, int(H), _dptr(S) if S.size else
+                                  ctypes.cast(None, ctypes.POINTER(ctypes.c_double)))
+    return S[:m]
+
+
 def log_sf_chi2_2w(x: float, w: int) -> float:
     return lib().oracle_log_sf_chi2_2w(float(x), int(w))
 
@@ -207,14 +223,16 @@ W_LOG2 = 1
 
 def search(spec, zmax: int, chunk: int, sigma: float, norm_block: int = 0, mode: int = NORM_MOM,
            ntrials: float = 0.0, tables: bool = False, cap: int = None,
-           width_search: int = W_ALL) -> SearchResult:
-    """Full search of one spectrum; candidates in (chunk, width) order."""
+           width_search: int = W_ALL, numharm: int = 1) -> SearchResult:
+    """Full search of one spectrum; candidates in (stage, chunk, width) order.
+    With numharm > 1 the harmonic stages H = 1..numharm are searched and each
+    candidate carries its stage in ``harm``; tables are those of stage 1."""
     s = _as_spec(spec)
     n = s.shape[0]
     nc = (n + chunk - 1) // chunk
     if cap is None:
-        cap = nc * zmax
-    out = np.zeros(cap, dtype=CAND_DTYPE)
+        cap = sum(((n // H) + chunk - 1) // chunk for H in range(1, max(numharm, 1) + 1)) * zmax
+    out = np.zeros(max(cap, 1), dtype=CAND_DTYPE)
     M = I = P = None
     mp = ip = pp = None
     if tables:
@@ -222,9 +240,10 @@ def search(spec, zmax: int, chunk: int, sigma: float, norm_block: int = 0, mode:
         I = np.empty((nc, zmax), dtype=np.int64)
         P = np.empty(n)
         mp, ip, pp = _dptr(M), I.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(P)
-    cnt = lib().oracle_search(s.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, zmax, chunk,
-                              sigma, norm_block, mode, ntrials, width_search, cap,
-                              out.ctypes.data_as(ctypes.POINTER(_Cand)), mp, ip, pp)
+    cnt = lib().oracle_search_harm(s.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, zmax,
+                                   chunk, sigma, norm_block, mode, ntrials, width_search,
+                                   max(int(numharm), 1), cap,
+                                   out.ctypes.data_as(ctypes.POINTER(_Cand)), mp, ip, pp)
     if cnt < 0:
         raise ValueError("oracle_search rejected its arguments")
     return SearchResult(out[:min(cnt, cap)].copy(), M, I, P)

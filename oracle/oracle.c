@@ -18,7 +18,10 @@
  *   4. per-chunk maxima for every width (appendix algorithm "Boxcar Filtering
  *      Process");
  *   5. significance: chi-square survival with 2w degrees of freedom,
- *      Bonferroni correction, Gaussian-equivalent sigma (section 2.2.3).
+ *      Bonferroni correction, Gaussian-equivalent sigma (section 2.2.3);
+ *   optionally, between steps 2 and 3, harmonic summing (section 2.3 and the
+ *      appendix algorithm "Harmonic Sum Decimation"): stage H searches the
+ *      sum of the power decimated by 1..H, with H(H+1) w degrees of freedom.
  *
  * Readings where the paper is silent or garbled (each is listed in the
  * design notes):
@@ -33,7 +36,11 @@
  *   - a window exists only when it fits: i + w <= n (output length n - k + 1
  *     in section 2.2.5);
  *   - argmax ties go to the smallest bin;
- *   - ntrials defaults to nbins * (number of searched widths);
+ *   - ntrials defaults to nbins * (number of searched widths); with harmonic
+ *     summing, per stage, to the stage's length times the searched widths;
+ *   - harmonic stage H has floor(n / H) bins (the bounds of the decimation
+ *     algorithm), is chunked and searched like the power itself, and its
+ *     candidates' bins are the stage's (the fundamental's) r-bins;
  *   - logarithms are natural.
  *
  * Parity of every function here is pinned by the CPU tests against
@@ -321,7 +328,7 @@ typedef struct {
   int64_t chunk;  /* chunk index */
   int64_t bin;    /* window start (left edge), 0-based */
   int32_t width;  /* 1..zmax */
-  int32_t pad;
+  int32_t harm;   /* harmonic stage H the window was found on (1: the power itself) */
   double power;   /* Y_width[bin] */
   double sigma;   /* Bonferroni-corrected Gaussian-equivalent sigma */
   double logp;    /* corrected log p */
@@ -338,66 +345,132 @@ static int width_is_searched(int w, int width_search) {
   return 1;
 }
 
-/* Run steps 1-5 on one spectrum and emit, in (chunk, width) order, every
- * per-chunk maximum of a searched width whose corrected significance reaches
- * sigma_thresh.  ntrials <= 0 means nbins * (number of searched widths).
- * Writes at most `cap` candidates to `out` and returns the total count, or
- * -1 on invalid arguments or allocation failure.  If M_out / I_out are
- * non-null they receive the full (nchunks x zmax) maxima tables and P_out
- * the normalised power. */
-int64_t oracle_search(const float *spec, int64_t n, int zmax, int64_t chunk, double sigma_thresh,
-                      int64_t norm_block, int mode, double ntrials, int width_search, int64_t cap,
-                      oracle_candidate *out, double *M_out, int64_t *I_out, double *P_out) {
-  if (!spec || n < 1 || zmax < 1 || chunk < 1) return -1;
-  if (norm_block <= 0) norm_block = chunk;
-  if (norm_block > n || zmax > n) return -1;
-  if (ntrials <= 0.0) {
-    int searched = 0;
-    for (int w = 1; w <= zmax; ++w) searched += width_is_searched(w, width_search);
-    ntrials = (double)n * (searched > 0 ? searched : 1);
+/* Harmonic summing (section 2.3; appendix algorithm "Harmonic Sum
+ * Decimation").  Decimating the power spectrum by h sums h adjacent,
+ * non-overlapping bins, D_h[r] = P[h r] + ... + P[h r + h - 1].  Stage H adds
+ * D_1 .. D_H aligned at bin 0 over their common length m = floor(n / H):
+ *     S_H[r] = D_1[r] + D_2[r] + ... + D_H[r],   r = 0 .. m - 1,
+ * which is chi-square with 2 + 4 + ... + 2H = H(H+1) degrees of freedom under
+ * the noise model.  Writes S (m doubles) and returns m. */
+int64_t oracle_harmonic_sum(const double *P, int64_t n, int H, double *S) {
+  if (H < 1) return 0;
+  int64_t m = n / H;
+  for (int64_t r = 0; r < m; ++r) {
+    double s = 0.0;
+    for (int h = 1; h <= H; ++h) {
+      double d = 0.0;
+      for (int j = 0; j < h; ++j) d += P[(int64_t)h * r + j];
+      s += d;
+    }
+    S[r] = s;
   }
-  int64_t nchunks = (n + chunk - 1) / chunk;
-  double *re = (double *)malloc((size_t)n * sizeof(double));
-  double *im = (double *)malloc((size_t)n * sizeof(double));
-  double *P = P_out ? P_out : (double *)malloc((size_t)n * sizeof(double));
+  return m;
+}
+
+/* Search one power series (one harmonic stage): per-chunk maxima of every
+ * width, significance with H(H+1) w degrees of freedom (a width-w boxcar of
+ * chi^2(H(H+1)) values), and emission of the maxima of searched widths whose
+ * corrected significance reaches the threshold, in (chunk, width) order.
+ * Appends to out (at most cap - *count entries) and advances *count by the
+ * number found. */
+static int search_stage(const double *S, int64_t m, int H, int zmax, int64_t chunk,
+                        double sigma_thresh, double ntrials, int width_search, int64_t cap,
+                        oracle_candidate *out, int64_t *count, double *M_out, int64_t *I_out) {
+  int64_t nchunks = (m + chunk - 1) / chunk;
   double *M = M_out ? M_out : (double *)malloc((size_t)(nchunks * zmax) * sizeof(double));
   int64_t *I = I_out ? I_out : (int64_t *)malloc((size_t)(nchunks * zmax) * sizeof(int64_t));
   double *lp = (double *)malloc((size_t)(nchunks * zmax) * sizeof(double));
+  int ok = M && I && lp;
+  if (ok) {
+    const int dof_half = H * (H + 1) / 2;  /* chi^2(2 w dof_half) */
+    oracle_chunk_maxima(S, m, zmax, chunk, M, I);
+    double lthresh = oracle_log_norm_sf(sigma_thresh);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t e = 0; e < nchunks * zmax; ++e) {
+      int w = (int)(e % zmax) + 1;
+      lp[e] = I[e] >= 0 ? oracle_log_p_corrected(M[e], w * dof_half, ntrials) : 0.0;
+    }
+    for (int64_t e = 0; e < nchunks * zmax; ++e) {
+      if (I[e] < 0 || !width_is_searched((int)(e % zmax) + 1, width_search)) continue;
+      if (!(lp[e] <= lthresh) || !(lp[e] < 0.0)) continue;
+      if (*count < cap && out) {
+        oracle_candidate *o = &out[*count];
+        o->chunk = e / zmax;
+        o->bin = I[e];
+        o->width = (int32_t)(e % zmax) + 1;
+        o->harm = H;
+        o->power = M[e];
+        o->logp = lp[e];
+        o->sigma = oracle_sigma_from_logp(lp[e]);
+      }
+      ++*count;
+    }
+  }
+  if (!M_out) free(M);
+  if (!I_out) free(I);
+  free(lp);
+  return ok ? 0 : -1;
+}
+
+/* Run the whole search on one spectrum: normalisation, power, and for each
+ * harmonic stage H = 1 .. numharm (numharm <= 1: the power alone) the
+ * boxcars, per-chunk maxima and threshold.  Emits, in (stage, chunk, width)
+ * order, every per-chunk maximum of a searched width whose corrected
+ * significance reaches sigma_thresh.  ntrials <= 0 means, per stage, the
+ * stage's length times the number of searched widths.  Writes at most `cap`
+ * candidates to `out` and returns the total count, or -1 on invalid
+ * arguments or allocation failure.  If M_out / I_out are non-null they
+ * receive the (nchunks x zmax) maxima tables of stage 1 and P_out the
+ * normalised power. */
+int64_t oracle_search_harm(const float *spec, int64_t n, int zmax, int64_t chunk,
+                           double sigma_thresh, int64_t norm_block, int mode, double ntrials,
+                           int width_search, int numharm, int64_t cap, oracle_candidate *out,
+                           double *M_out, int64_t *I_out, double *P_out) {
+  if (!spec || n < 1 || zmax < 1 || chunk < 1) return -1;
+  if (numharm < 1) numharm = 1;
+  if (norm_block <= 0) norm_block = chunk;
+  if (norm_block > n || zmax > n) return -1;
+  int searched = 0;
+  for (int w = 1; w <= zmax; ++w) searched += width_is_searched(w, width_search);
+  if (searched == 0) searched = 1;
+  double *re = (double *)malloc((size_t)n * sizeof(double));
+  double *im = (double *)malloc((size_t)n * sizeof(double));
+  double *P = P_out ? P_out : (double *)malloc((size_t)n * sizeof(double));
+  double *S = numharm > 1 ? (double *)malloc((size_t)(n / 2 + 1) * sizeof(double)) : NULL;
   int64_t count = -1;
-  if (!re || !im || !P || !M || !I || !lp) goto done;
+  if (!re || !im || !P || (numharm > 1 && !S)) goto done;
   if (oracle_normalise(spec, n, norm_block, mode, re, im, NULL) != 0) goto done;
   oracle_power(re, im, n, P);
-  oracle_chunk_maxima(P, n, zmax, chunk, M, I);
-  double lthresh = oracle_log_norm_sf(sigma_thresh);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t e = 0; e < nchunks * zmax; ++e) {
-    int w = (int)(e % zmax) + 1;
-    lp[e] = I[e] >= 0 ? oracle_log_p_corrected(M[e], w, ntrials) : 0.0;
-  }
   count = 0;
-  for (int64_t e = 0; e < nchunks * zmax; ++e) {
-    if (I[e] < 0 || !width_is_searched((int)(e % zmax) + 1, width_search)) continue;
-    if (!(lp[e] <= lthresh) || !(lp[e] < 0.0)) continue;
-    if (count < cap && out) {
-      oracle_candidate *o = &out[count];
-      o->chunk = e / zmax;
-      o->bin = I[e];
-      o->width = (int32_t)(e % zmax) + 1;
-      o->pad = 0;
-      o->power = M[e];
-      o->logp = lp[e];
-      o->sigma = oracle_sigma_from_logp(lp[e]);
+  for (int H = 1; H <= numharm; ++H) {
+    const double *X = P;
+    int64_t m = n;
+    if (H > 1) {
+      m = oracle_harmonic_sum(P, n, H, S);
+      X = S;
     }
-    ++count;
+    if (m < 1) break;
+    double nt = ntrials > 0.0 ? ntrials : (double)m * searched;
+    if (search_stage(X, m, H, zmax, chunk, sigma_thresh, nt, width_search, cap, out, &count,
+                     H == 1 ? M_out : NULL, H == 1 ? I_out : NULL) != 0) {
+      count = -1;
+      goto done;
+    }
   }
 done:
   free(re);
   free(im);
   if (!P_out) free(P);
-  if (!M_out) free(M);
-  if (!I_out) free(I);
-  free(lp);
+  free(S);
   return count;
+}
+
+/* The search without harmonic summing (numharm = 1). */
+int64_t oracle_search(const float *spec, int64_t n, int zmax, int64_t chunk, double sigma_thresh,
+                      int64_t norm_block, int mode, double ntrials, int width_search, int64_t cap,
+                      oracle_candidate *out, double *M_out, int64_t *I_out, double *P_out) {
+  return oracle_search_harm(spec, n, zmax, chunk, sigma_thresh, norm_block, mode, ntrials,
+                            width_search, 1, cap, out, M_out, I_out, P_out);
 }
 
 /* Number of OpenMP threads a parallel region of this library uses. */

@@ -34,11 +34,13 @@ PULSCAN_W_LOG2 = 1
 class pulscan_candidate(ctypes.Structure):
     _fields_ = [("spectrum", ctypes.c_uint32), ("bin", ctypes.c_uint32),
                 ("width", ctypes.c_uint32), ("power", ctypes.c_float),
-                ("sigma", ctypes.c_float), ("chunk", ctypes.c_uint32)]
+                ("sigma", ctypes.c_float), ("chunk", ctypes.c_uint32),
+                ("harmonics", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 CANDIDATE_DTYPE = np.dtype([("spectrum", np.uint32), ("bin", np.uint32), ("width", np.uint32),
-                            ("power", np.float32), ("sigma", np.float32), ("chunk", np.uint32)])
+                            ("power", np.float32), ("sigma", np.float32), ("chunk", np.uint32),
+                            ("harmonics", np.uint32), ("reserved", np.uint32)])
 
 
 class pulscan_candidates(ctypes.Structure):
@@ -51,12 +53,13 @@ class pulscan_opts(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int32), ("norm_block", ctypes.c_int32),
                 ("ntrials", ctypes.c_double), ("width_search", ctypes.c_int32),
                 ("async_", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("dense", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dense", ctypes.c_int32), ("numharm", ctypes.c_int32),
+                ("best_per_chunk", ctypes.c_int32), ("rblock", ctypes.c_int32)]
 
 
-assert ctypes.sizeof(pulscan_candidate) == 24 == CANDIDATE_DTYPE.itemsize
+assert ctypes.sizeof(pulscan_candidate) == 32 == CANDIDATE_DTYPE.itemsize
 assert ctypes.sizeof(pulscan_candidates) == 40
-assert ctypes.sizeof(pulscan_opts) == 40
+assert ctypes.sizeof(pulscan_opts) == 48
 
 # every function the header declares: name -> (restype, argtypes)
 _vp, _sz, _i, _f, _d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float, ctypes.c_double
@@ -140,12 +143,21 @@ def pulscan_opts_default() -> pulscan_opts:
     return o
 
 
+def worst_count(nbins: int, zmax: int, chunk: int, numharm: int = 1) -> int:
+    """Most candidates one spectrum can yield: one per (stage, chunk, width)."""
+    if chunk <= 0 or zmax <= 0:
+        return 0
+    return sum(((nbins // H) + chunk - 1) // chunk for H in range(1, max(numharm, 1) + 1)) * zmax
+
+
 def make_opts(norm: int = PULSCAN_NORM_MOM, norm_block: int = 0, ntrials: float = 0.0,
               width_search: int = PULSCAN_W_ALL, async_: bool = False, stream=None,
-              dense: bool = False) -> pulscan_opts:
+              dense: bool = False, numharm: int = 1, best_per_chunk: bool = False,
+              rblock: int = 0) -> pulscan_opts:
     o = pulscan_opts_default()
     o.norm, o.norm_block, o.ntrials = norm, norm_block, ntrials
     o.width_search, o.async_, o.dense = width_search, int(bool(async_)), int(bool(dense))
+    o.numharm, o.best_per_chunk, o.rblock = int(numharm), int(bool(best_per_chunk)), int(rblock)
     if stream is not None:
         o.stream = stream if isinstance(stream, int) else stream.cuda_stream
     return o
@@ -181,14 +193,14 @@ class Context:
         """Search one spectrum.  Returns (candidates, true_count).
 
         Host output by default (a numpy structured array of CANDIDATE_DTYPE).
-        With ``out_device`` (a CUDA uint8 tensor of capacity*24 bytes) the
+        With ``out_device`` (a CUDA uint8 tensor of capacity*32 bytes) the
         candidates stay on the device and the array returned is None.
         """
         ptr, n = _spectrum_ptr(spectrum)
         if opts is None:
             opts = pulscan_opts_default()
         if capacity is None:
-            capacity = ((n + chunk - 1) // chunk) * zmax if chunk > 0 and zmax > 0 else 0
+            capacity = worst_count(n, zmax, chunk, opts.numharm)
         out = pulscan_candidates()
         host = None
         if out_device is not None:
@@ -216,13 +228,13 @@ class Context:
         ptrs = (ctypes.c_void_p * ns)()
         ns_arr = (ctypes.c_uint64 * ns)()
         zs = (ctypes.c_int32 * ns)()
+        if opts is None:
+            opts = pulscan_opts_default()
         cap_auto = 0
         for i, (s, z) in enumerate(zip(spectra, zmax)):
             p, n = _spectrum_ptr(s)
             ptrs[i], ns_arr[i], zs[i] = p, n, int(z)
-            cap_auto += ((n + max(chunk, 64) - 1) // max(chunk, 64)) * max(int(z), 0)
-        if opts is None:
-            opts = pulscan_opts_default()
+            cap_auto += worst_count(n, int(z), max(chunk, 64), opts.numharm)
         if capacity is None:
             capacity = cap_auto
         out = pulscan_candidates()
@@ -310,7 +322,7 @@ def pulscan_search(spectrum, zmax: int, chunk: int, sigma_thresh: float,
     """The plain call on the library's default context: (candidates, true_count)."""
     ptr, n = _spectrum_ptr(spectrum)
     if capacity is None:
-        capacity = ((n + chunk - 1) // chunk) * zmax if chunk > 0 and zmax > 0 else 0
+        capacity = worst_count(n, zmax, chunk)
     host = np.zeros(max(capacity, 1), dtype=CANDIDATE_DTYPE)
     out = pulscan_candidates()
     out.data = host.ctypes.data

@@ -38,6 +38,7 @@ struct ThrKey {
 struct pulscan_ctx {
   int device = 0;
   DevBuf thr, pool, tile_word, tile_prefix, counters, outbuf, descs, jobs;
+  DevBuf allbuf, hpow, hsum, hjobs;  // best-per-chunk scratch; harmonic power, sums, jobs
   uint32_t gen = 0;  // launch generation of the per-tile count words
   ThrKey thr_key;
   // pinned staging of batched descriptors / threshold jobs
@@ -63,6 +64,7 @@ struct Counters {
   uint32_t head;
   uint32_t done;
   uint32_t pad;
+  unsigned long long best;  // candidates kept by the best-per-chunk pass
 };
 
 #define HIP_TRY(call)                       \
@@ -151,6 +153,9 @@ int check_spectrum(const void *x, uint64_t n, int zmax, int chunk, const pulscan
   if (o.norm_block < 0) return PULSCAN_EINVAL;
   if (!(o.ntrials == 0.0 || (isfinite(o.ntrials) && o.ntrials >= 1.0))) return PULSCAN_EINVAL;
   if (o.dense != 0 && o.dense != 1) return PULSCAN_EINVAL;
+  if (o.numharm < 0 || o.numharm > kMaxHarm) return PULSCAN_EINVAL;
+  if (o.best_per_chunk != 0 && o.best_per_chunk != 1) return PULSCAN_EINVAL;
+  if (o.rblock < 0) return PULSCAN_EINVAL;
   const uint64_t B = o.norm_block > 0 ? (uint64_t)o.norm_block : (uint64_t)chunk;
   if (n < B || n < (uint64_t)zmax) return PULSCAN_EINVAL;
   if (o.norm == PULSCAN_NORM_MOM && !is_pow4(B)) return PULSCAN_EINVAL;
@@ -188,12 +193,17 @@ struct SpecIn {
   const void *x;
   uint64_t n;
   uint32_t zmax;
+  uint32_t dofmul = 1;     // chi^2(2 w dofmul) per width-w boxcar
+  uint32_t spec_id = 0;    // reported spectrum index
+  uint32_t harm = 1;       // reported harmonic stage
+  float *aux = nullptr;    // power mode: output power
 };
 
-enum RunKind { kRunSearch, kRunTables, kRunFromPower };
+enum RunKind { kRunSearch, kRunTables, kRunPower };
 
 struct RunArgs {
   RunKind kind = kRunSearch;
+  bool from_power = false;  // the series are float power (no normalisation)
   uint32_t chunk = 0, block = 0;
   float sigma = 0.f;
   pulscan_opts opts{};
@@ -204,12 +214,15 @@ struct RunArgs {
   float *stats_out = nullptr;
 };
 
-int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
-  HIP_TRY(hipSetDevice(ctx->device));
+// One fused launch of the bank kernel over a batch of series, then (search
+// mode) the emission of the candidates and, on request, the best-per-chunk
+// pass.
+int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   hipStream_t stream = (hipStream_t)a.opts.stream;
   const int nspec = (int)specs.size();
-  const bool debug = a.kind != kRunSearch;
-  const int ws = debug ? PULSCAN_W_ALL : a.opts.width_search;
+  const bool search = a.kind == kRunSearch;
+  const bool power_only = a.kind == kRunPower;
+  const int ws = search ? a.opts.width_search : PULSCAN_W_ALL;
 
   uint32_t zmax_max = 0;
   uint64_t n_min = ~0ull;
@@ -226,11 +239,16 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   uint32_t zc_max = 0;
   for (int s = 0; s < nspec; ++s) {
     SpecDesc &d = descs[s];
+    d = SpecDesc{};
     d.x = reinterpret_cast<const float2 *>(specs[s].x);
+    d.aux = specs[s].aux;
     d.n = (uint32_t)specs[s].n;
     d.zmax = specs[s].zmax;
     d.zc = round_widths(d.zmax, g.K);
     d.nchunks = (uint32_t)((specs[s].n + a.chunk - 1) / a.chunk);
+    d.dofmul = specs[s].dofmul;
+    d.spec_id = specs[s].spec_id;
+    d.harm = specs[s].harm;
     d.tile_begin = tiles;
     tiles += (specs[s].n + g.tile - 1) / g.tile;
     if (a.opts.ntrials > 0.0) {
@@ -243,36 +261,39 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   }
 
   // thresholds: table s at thr + s * zc_max
-  const void *thr_before = ctx->thr.p;
-  int st = grow(ctx, ctx->thr, (size_t)nspec * zc_max * sizeof(float), false);
-  if (st) return st;
-  if (ctx->thr.p != thr_before) ctx->thr_key.valid = false;
-  float *thr = static_cast<float *>(ctx->thr.p);
-  for (int s = 0; s < nspec; ++s) descs[s].thr = thr + (size_t)s * zc_max;
-  ThrKey key;
-  key.valid = nspec == 1;
-  key.zmax = descs[0].zmax;
-  key.zc = descs[0].zc;
-  key.sigma = a.sigma;
-  key.ntrials = descs[0].ntrials;
-  key.width_search = ws;
-  key.debug = debug ? 1 : 0;
-  if (!(nspec == 1 && key == ctx->thr_key)) {
-    std::vector<ThreshJob> jobs(nspec);
-    for (int s = 0; s < nspec; ++s)
-      jobs[s] = ThreshJob{const_cast<float *>(descs[s].thr), descs[s].zmax, descs[s].zc,
-                          descs[s].ntrials};
-    const ThreshJob *jobs_dev = nullptr;
-    if (nspec > 1) {
-      st = grow(ctx, ctx->jobs, jobs.size() * sizeof(ThreshJob), false);
-      if (st) return st;
-      st = upload(ctx, ctx->jobs.p, jobs.data(), jobs.size() * sizeof(ThreshJob), stream);
-      if (st) return st;
-      jobs_dev = static_cast<const ThreshJob *>(ctx->jobs.p);
+  int st = PULSCAN_OK;
+  if (!power_only) {
+    const void *thr_before = ctx->thr.p;
+    st = grow(ctx, ctx->thr, (size_t)nspec * zc_max * sizeof(float), false);
+    if (st) return st;
+    if (ctx->thr.p != thr_before) ctx->thr_key.valid = false;
+    float *thr = static_cast<float *>(ctx->thr.p);
+    for (int s = 0; s < nspec; ++s) descs[s].thr = thr + (size_t)s * zc_max;
+    ThrKey key;
+    key.valid = nspec == 1 && descs[0].dofmul == 1;
+    key.zmax = descs[0].zmax;
+    key.zc = descs[0].zc;
+    key.sigma = a.sigma;
+    key.ntrials = descs[0].ntrials;
+    key.width_search = ws;
+    key.debug = search ? 0 : 1;
+    if (!(key.valid && key == ctx->thr_key)) {
+      std::vector<ThreshJob> jobs(nspec);
+      for (int s = 0; s < nspec; ++s)
+        jobs[s] = ThreshJob{const_cast<float *>(descs[s].thr), descs[s].zmax, descs[s].zc,
+                            descs[s].ntrials, descs[s].dofmul, 0u};
+      const ThreshJob *jobs_dev = nullptr;
+      if (nspec > 1) {
+        st = grow(ctx, ctx->jobs, jobs.size() * sizeof(ThreshJob), false);
+        if (st) return st;
+        st = upload(ctx, ctx->jobs.p, jobs.data(), jobs.size() * sizeof(ThreshJob), stream);
+        if (st) return st;
+        jobs_dev = static_cast<const ThreshJob *>(ctx->jobs.p);
+      }
+      HIP_TRY(launch_thresholds(jobs_dev, jobs[0], nspec, zc_max, (double)a.sigma, ws, key.debug,
+                                stream));
+      ctx->thr_key = key.valid ? key : ThrKey{};
     }
-    HIP_TRY(launch_thresholds(jobs_dev, jobs[0], nspec, zc_max, (double)a.sigma, ws, key.debug,
-                              stream));
-    ctx->thr_key = key;
   }
 
   BankParams bp{};
@@ -285,8 +306,8 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   bp.zmax_max = zmax_max;
   bp.nseg_lds = g.nseg_lds;
   bp.zc_max_pad = g.zc_max_pad;
-  bp.mode = debug ? kModeTables : kModeSearch;
-  bp.from_power = a.kind == kRunFromPower ? 1 : 0;
+  bp.mode = search ? kModeSearch : power_only ? kModePower : kModeTables;
+  bp.from_power = a.from_power ? 1 : 0;
   bp.dense = a.opts.dense ? 1 : 0;
   bp.M = a.M;
   bp.I = a.I;
@@ -298,8 +319,9 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   for (const SpecDesc &d : descs) worst += (uint64_t)d.nchunks * d.zmax;
   if (worst >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
   const uint32_t pool_cap = (uint32_t)(worst < (uint64_t)kPoolMax ? (worst ? worst : 1) : kPoolMax);
+  const bool best = search && a.opts.best_per_chunk;
   Counters *cnt = nullptr;
-  if (!debug) {
+  if (search) {
     st = grow(ctx, ctx->pool, (size_t)pool_cap * sizeof(StageEntry), false);
     if (st) return st;
     st = grow(ctx, ctx->tile_word, tiles * sizeof(unsigned long long), true);
@@ -318,7 +340,7 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
     bp.gen = ctx->gen;
     bp.tile_prefix = static_cast<uint32_t *>(ctx->tile_prefix.p);
     bp.total = &cnt->total;
-    bp.total2 = reinterpret_cast<unsigned long long *>(a.out->count_device);
+    bp.total2 = best ? nullptr : reinterpret_cast<unsigned long long *>(a.out->count_device);
     bp.overflow = &cnt->overflow;
   }
 
@@ -336,24 +358,26 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   }
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->timing) {
+  if (ctx->timing && !power_only) {
     e0 = take_event(ctx);
     e1 = take_event(ctx);
     if (!e0 || !e1) return PULSCAN_EHIP;
     HIP_TRY(hipEventRecord(e0, stream));
   }
   HIP_TRY(launch_bank(g, bp, tiles, stream));
-  if (ctx->timing) {
+  if (e1) {
     HIP_TRY(hipEventRecord(e1, stream));
     ctx->ev_rec.emplace_back(e0, e1);
   }
 
-  if (debug) {
+  if (power_only) return PULSCAN_OK;  // ordered before the caller's next launch
+  if (!search) {
     HIP_TRY(hipStreamSynchronize(stream));
     return PULSCAN_OK;
   }
 
-  // emit into the caller's device buffer, or into ours for a host copy
+  // emit into the caller's device buffer, or into ours for a host copy; with
+  // best_per_chunk everything goes to scratch first
   pulscan_candidates *out = a.out;
   pulscan_candidate *dst = out->data;
   uint64_t cap = out->capacity;
@@ -371,21 +395,31 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
   ep.tile_prefix = bp.tile_prefix;
   ep.total = bp.total;
   ep.chunk = a.chunk;
+  ep.rblock = (uint32_t)a.opts.rblock;
   ep.out = dst;
   ep.capacity = cap;
-  const uint64_t work = cap < worst ? cap : worst;
+  if (best) {
+    st = grow(ctx, ctx->allbuf, (size_t)pool_cap * sizeof(pulscan_candidate), false);
+    if (st) return st;
+    ep.out = static_cast<pulscan_candidate *>(ctx->allbuf.p);
+    ep.capacity = pool_cap;
+  }
+  const uint64_t work = ep.capacity < worst ? ep.capacity : worst;
   const uint32_t egrid = (uint32_t)(work / 256 + 1 < 512 ? work / 256 + 1 : 512);
   HIP_TRY(launch_emit(ep, descs[0], egrid, stream));
+  if (best)
+    HIP_TRY(launch_best(ep.out, bp.total, pool_cap, dst, cap, &cnt->best,
+                        reinterpret_cast<unsigned long long *>(out->count_device), stream));
 
   if (a.opts.async) return PULSCAN_OK;
 
   Counters hc{};
   HIP_TRY(hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  const unsigned long long total = hc.total;
-  out->count = total;
   if (hc.overflow == 2) return PULSCAN_EHIP;  // a tile's count never arrived
   if (hc.overflow) return PULSCAN_ENOMEM;
+  const unsigned long long total = best ? hc.best : hc.total;
+  out->count = total;
   if (!out->on_device) {
     const uint64_t ncopy = total < cap ? total : cap;
     if (ncopy) {
@@ -395,6 +429,83 @@ int run(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
     }
   }
   return total > out->capacity ? PULSCAN_EOVERFLOW : PULSCAN_OK;
+}
+
+// Harmonic summing: the normalised power of every spectrum is written once,
+// stages 2..numharm are built from it, and all stages of all spectra are
+// searched in one fused launch (power input), stage by stage in canonical
+// order.
+int run_harmonics(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
+  hipStream_t stream = (hipStream_t)a.opts.stream;
+  const uint32_t nh = (uint32_t)a.opts.numharm;
+  const int nspec = (int)specs.size();
+  uint64_t pn = 0, sn = 0;
+  uint32_t n_max = 0;
+  for (const SpecIn &s : specs) {
+    pn += s.n;
+    sn += harmonic_offset(s.n, nh + 1);
+    n_max = s.n > n_max ? (uint32_t)s.n : n_max;
+  }
+  int st = grow(ctx, ctx->hpow, pn * sizeof(float), false);
+  if (st) return st;
+  st = grow(ctx, ctx->hsum, (sn ? sn : 1) * sizeof(float), false);
+  if (st) return st;
+  float *P = static_cast<float *>(ctx->hpow.p);
+  float *S = static_cast<float *>(ctx->hsum.p);
+
+  // 1. normalised power of every spectrum
+  std::vector<SpecIn> ps(specs);
+  std::vector<HarmJob> jobs(nspec);
+  uint64_t po = 0, so = 0;
+  for (int s = 0; s < nspec; ++s) {
+    ps[s].aux = P + po;
+    jobs[s] = HarmJob{P + po, S + so, (uint32_t)specs[s].n, nh};
+    po += specs[s].n;
+    so += harmonic_offset(specs[s].n, nh + 1);
+  }
+  RunArgs ap = a;
+  ap.kind = kRunPower;
+  st = run_core(ctx, ps, ap);
+  if (st) return st;
+
+  // 2. stages 2..numharm
+  const HarmJob *jobs_dev = nullptr;
+  if (nspec > 1) {
+    st = grow(ctx, ctx->hjobs, jobs.size() * sizeof(HarmJob), false);
+    if (st) return st;
+    st = upload(ctx, ctx->hjobs.p, jobs.data(), jobs.size() * sizeof(HarmJob), stream);
+    if (st) return st;
+    jobs_dev = static_cast<const HarmJob *>(ctx->hjobs.p);
+  }
+  HIP_TRY(launch_harmonics(jobs_dev, jobs[0], nspec, n_max, stream));
+
+  // 3. every stage of every spectrum, searched on its power
+  std::vector<SpecIn> stages;
+  for (int s = 0; s < nspec; ++s) {
+    for (uint32_t H = 1; H <= nh; ++H) {
+      const uint64_t m = specs[s].n / H;
+      if (m == 0) break;
+      SpecIn si{};
+      si.x = H == 1 ? (const void *)jobs[s].P
+                    : (const void *)(jobs[s].S + harmonic_offset(specs[s].n, H));
+      si.n = m;
+      si.zmax = specs[s].zmax;
+      si.dofmul = H * (H + 1) / 2;
+      si.spec_id = specs[s].spec_id;
+      si.harm = H;
+      stages.push_back(si);
+    }
+  }
+  RunArgs as = a;
+  as.from_power = true;
+  return run_core(ctx, stages, as);
+}
+
+int run(pulscan_ctx *ctx, std::vector<SpecIn> specs, const RunArgs &a) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  for (size_t s = 0; s < specs.size(); ++s) specs[s].spec_id = (uint32_t)s;
+  if (a.kind == kRunSearch && a.opts.numharm > 1) return run_harmonics(ctx, specs, a);
+  return run_core(ctx, specs, a);
 }
 
 std::mutex g_default_mu;
@@ -421,6 +532,7 @@ void pulscan_opts_default(pulscan_opts *o) {
   memset(o, 0, sizeof(*o));
   o->norm = PULSCAN_NORM_MOM;
   o->width_search = PULSCAN_W_ALL;
+  o->numharm = 1;
 }
 
 int pulscan_ctx_create(pulscan_ctx **out, int device) {
@@ -446,9 +558,9 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DevBuf *bufs[] = {&ctx->thr,         &ctx->pool,     &ctx->tile_word,
-                    &ctx->tile_prefix, &ctx->counters, &ctx->outbuf,     &ctx->descs,
-                    &ctx->jobs};
+  DevBuf *bufs[] = {&ctx->thr,    &ctx->pool,   &ctx->tile_word, &ctx->tile_prefix,
+                    &ctx->counters, &ctx->outbuf, &ctx->descs,  &ctx->jobs,
+                    &ctx->allbuf, &ctx->hpow,   &ctx->hsum,     &ctx->hjobs};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -563,7 +675,8 @@ int pulscan_debug_bank_from_power(pulscan_ctx *ctx, const float *power, size_t n
   const uint64_t nchunks = (nbins + chunk - 1) / chunk;
   if (nchunks * (uint64_t)zmax >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
   RunArgs a;
-  a.kind = kRunFromPower;
+  a.kind = kRunTables;
+  a.from_power = true;
   a.chunk = (uint32_t)chunk;
   a.block = 64;
   pulscan_opts_default(&a.opts);
@@ -585,7 +698,7 @@ int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, doub
     (void)hipGetLastError();
     return PULSCAN_ENOMEM;
   }
-  ThreshJob job{static_cast<float *>(tmp.p), (uint32_t)zmax, (uint32_t)zmax, ntrials};
+  ThreshJob job{static_cast<float *>(tmp.p), (uint32_t)zmax, (uint32_t)zmax, ntrials, 1u, 0u};
   int st = PULSCAN_OK;
   if (launch_thresholds(nullptr, job, 1, (uint32_t)zmax, (double)sigma_thresh, width_search, 0,
                         nullptr) != hipSuccess ||

@@ -636,7 +636,8 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
     const uint32_t t0 = (uint32_t)(tg - d.tile_begin) * T;
     const uint32_t n = d.n, zmax = d.zmax, zc = d.zc;
     const uint32_t rem = n - t0;
-    const uint32_t need = min(T + zmax - 1, rem);
+    const bool power_only = p.mode == kModePower;
+    const uint32_t need = min(power_only ? T : T + zmax - 1, rem);
     const uint32_t nblk = zc / K;
     const uint32_t span = T + zc;  // tile bins the bank and the bound read
     const uint32_t bfirst = t0 / B, blast = (t0 + need - 1) / B;
@@ -657,6 +658,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       // behind the spectrum loads
       if (p.mode == kModeSearch) ticket = atomicAdd(p.done, 1u);
     }
+    if (!power_only) {
     for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
     for (uint32_t i = tid; i < zc; i += nthr) Tl[i] = d.thr[i];
     if (tid < 4) {
@@ -671,6 +673,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       for (int u = 1; u < K; ++u) m = fminf(m, d.thr[i * K + u]);
       Tb[i] = m * kBoundSlack;
     }
+    }
     // bins past the spectrum's end are -inf (no window may contain them);
     // halo bins beyond what any width <= zmax reads are 0 (read only by the
     // unrecorded widths zmax+1..zc and by the pruning bound)
@@ -681,7 +684,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       for (uint32_t i = tid; i < need; i += nthr) Pl[paddr<K>(i)] = pw[t0 + i];
     } else if (have) {
       const bool dbg = p.mode == kModeTables;
-      float *po = dbg ? p.P_out : nullptr;
+      float *po = power_only ? d.aux : dbg ? p.P_out : nullptr;
       float *so = dbg ? p.stats_out : nullptr;
       for (uint32_t b = bfirst + wave; b <= blast; b += nw) {
         if (b != bfirst + wave) load_block<EPL>(d.x, n, b, lane, bd);
@@ -689,6 +692,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       }
     }
     }
+    if (power_only) return;  // the power is written; nothing else to do
     __syncthreads();
 
     // --- bank ----------------------------------------------------------------

@@ -16,17 +16,23 @@ constexpr int kMaxThreads = 512;      // threads per workgroup of the bank kerne
 constexpr int kMaxTile = 16384;       // bins per tile
 constexpr uint32_t kPoolMax = 1u << 26;  // staging-pool entries per context (1 GiB)
 
-// One spectrum of a launch.  A device-resident array of these drives the
-// bank and finalise kernels; a single search is a batch of one.
+// One searched series of a launch: a spectrum, or one harmonic stage of a
+// spectrum (power input).  A device-resident array of these drives the bank
+// and emit kernels; a single series is a batch of one.
 struct SpecDesc {
   const float2 *x;        // complex spectrum (or, from-power mode, float power)
   const float *thr;       // per-width thresholds, zc entries (+inf beyond zmax)
-  uint64_t tile_begin;    // first global tile of this spectrum
+  float *aux;             // power mode: where the normalised power goes
+  uint64_t tile_begin;    // first global tile of this series
   double ntrials;         // Bonferroni factor
   uint32_t n;             // bins
   uint32_t zmax;          // widths 1..zmax
   uint32_t zc;            // zmax rounded up to the bank kernel's width block
   uint32_t nchunks;       // ceil(n / chunk)
+  uint32_t dofmul;        // degrees of freedom per width / 2: H(H+1)/2 for stage H
+  uint32_t spec_id;       // spectrum index reported in candidates
+  uint32_t harm;          // harmonic stage H reported in candidates
+  uint32_t pad;
 };
 
 // A staged candidate.  Each tile writes its own in (chunk, width) order to a
@@ -43,6 +49,7 @@ constexpr uint32_t kWidthBits = 12;  // zmax <= 4096
 enum BankMode : int {
   kModeSearch = 0,   // stage (chunk, width) maxima that reach the threshold
   kModeTables = 1,   // write every (chunk, width) maximum to M / I
+  kModePower = 2,    // normalise only: each series' power to its desc.aux
 };
 
 // Launch-wide parameters of the bank kernel.
@@ -108,6 +115,8 @@ struct ThreshJob {
   uint32_t zmax;
   uint32_t zc;
   double ntrials;
+  uint32_t dofmul;  // chi^2(2 w dofmul) for width w
+  uint32_t pad;
 };
 // jobs_dev == nullptr: one job, `single`.
 hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single, int njobs,
@@ -117,18 +126,45 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
 // Candidate f of the staging pool goes to out[tile_prefix[tile] + rank]
 // (when that is below capacity), with its FP64 significance.
 struct EmitParams {
-  const SpecDesc *descs;           // device table, or nullptr for one spectrum
+  const SpecDesc *descs;           // device table, or nullptr for one series
   int nspec;
   const StageEntry *pool;
   uint32_t pool_cap;
   const uint32_t *tile_prefix;
   const unsigned long long *total;
   uint32_t chunk;
+  uint32_t rblock;                 // > 0: report bin / rblock
   pulscan_candidate *out;
   uint64_t capacity;
 };
 hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t grid,
                        hipStream_t stream);
+
+// Best candidate per (spectrum, stage, chunk) of the canonical list `all`
+// (count *total, at most all_cap stored): out[k] is the highest-sigma
+// candidate of the k-th run of equal keys (the first on ties); the number of
+// runs goes to *count and, if non-null, *count2.  One workgroup.
+hipError_t launch_best(const pulscan_candidate *all, const unsigned long long *total,
+                       uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
+                       unsigned long long *count, unsigned long long *count2,
+                       hipStream_t stream);
+
+// Harmonic stages 2..numharm of one power series (section 2.3): S_H has
+// floor(n / H) bins and starts at S + sum_{h=2}^{H-1} floor(n / h).
+struct HarmJob {
+  const float *P;
+  float *S;
+  uint32_t n;
+  uint32_t numharm;
+};
+hipError_t launch_harmonics(const HarmJob *jobs_dev, const HarmJob &single, int njobs,
+                            uint32_t n_max, hipStream_t stream);
+inline uint64_t harmonic_offset(uint64_t n, uint32_t H) {
+  uint64_t off = 0;
+  for (uint32_t h = 2; h < H; ++h) off += n / h;
+  return off;
+}
+constexpr int kMaxHarm = 16;
 
 // Is width w searched under width_search?
 __host__ __device__ inline bool width_searched(uint32_t w, int width_search) {

@@ -117,7 +117,7 @@ __global__ void threshold_kernel(const ThreshJob *__restrict__ jobs, ThreshJob s
   else if (debug)
     out = -FLT_MAX;
   else
-    out = round_up_f32(power_threshold(sigma, w, jb.ntrials));
+    out = round_up_f32(power_threshold(sigma, w * jb.dofmul, jb.ntrials));
   jb.thr[w - 1] = out;
 }
 
@@ -156,16 +156,18 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
       }
       s = a;
     }
-    const double ntrials = p.nspec > 1 ? p.descs[s].ntrials : single.ntrials;
+    const SpecDesc &d = p.nspec > 1 ? p.descs[s] : single;
     const uint32_t w = (e.rank_width & ((1u << kWidthBits) - 1u)) + 1u;
-    const double lp = log_sf_chi2_even((double)e.power, w) + log(ntrials);
+    const double lp = log_sf_chi2_even((double)e.power, w * d.dofmul) + log(d.ntrials);
     pulscan_candidate c;
-    c.spectrum = (uint32_t)s;
-    c.bin = e.bin;
+    c.spectrum = d.spec_id;
+    c.bin = p.rblock ? e.bin / p.rblock : e.bin;
     c.width = w;
     c.power = e.power;
     c.sigma = (float)sigma_from_logp(lp < 0.0 ? lp : 0.0);
     c.chunk = e.bin / p.chunk;
+    c.harmonics = d.harm;
+    c.reserved = 0u;
     p.out[dest] = c;
   }
 }
@@ -173,6 +175,64 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
 hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t grid,
                        hipStream_t stream) {
   hipLaunchKernelGGL(emit_kernel, dim3(grid), dim3(kEmitThreads), 0, stream, p, single);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Best candidate per (spectrum, stage, chunk).  The list is in canonical
+// order, so each key is one contiguous run.  One workgroup walks the list in
+// rounds of kBestThreads: a thread whose entry starts a run picks the run's
+// highest sigma (the first on ties) and writes it at its run rank.
+
+constexpr int kBestThreads = 1024;
+
+__device__ __forceinline__ bool same_key(const pulscan_candidate &a, const pulscan_candidate &b) {
+  return a.spectrum == b.spectrum && a.harmonics == b.harmonics && a.chunk == b.chunk;
+}
+
+__global__ __launch_bounds__(kBestThreads) void best_kernel(
+    const pulscan_candidate *__restrict__ all, const unsigned long long *__restrict__ total_p,
+    uint64_t all_cap, pulscan_candidate *__restrict__ out, uint64_t capacity,
+    unsigned long long *count, unsigned long long *count2) {
+  __shared__ uint32_t wave_cnt[kBestThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned long long tot = *total_p;
+  const uint64_t n = tot < all_cap ? tot : all_cap;
+  uint64_t runs = 0;
+  for (uint64_t base = 0; base < n; base += kBestThreads) {
+    const uint64_t i = base + tid;
+    bool head = false;
+    if (i < n) head = i == 0 || !same_key(all[i - 1], all[i]);
+    const unsigned long long mask = __ballot(head);
+    if (lane == 0) wave_cnt[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint64_t before = 0, here = 0;
+    for (uint32_t v = 0; v < kBestThreads / 64; ++v) {
+      before += v < wave ? wave_cnt[v] : 0u;
+      here += wave_cnt[v];
+    }
+    if (head) {
+      const uint64_t rank = runs + before + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
+      uint64_t b = i;
+      for (uint64_t j = i + 1; j < n && same_key(all[i], all[j]); ++j)
+        if (all[j].sigma > all[b].sigma) b = j;
+      if (rank < capacity) out[rank] = all[b];
+    }
+    runs += here;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *count = runs;
+    if (count2) *count2 = runs;
+  }
+}
+
+hipError_t launch_best(const pulscan_candidate *all, const unsigned long long *total,
+                       uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
+                       unsigned long long *count, unsigned long long *count2,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(best_kernel, dim3(1), dim3(kBestThreads), 0, stream, all, total, all_cap,
+                     out, capacity, count, count2);
   return hipGetLastError();
 }
 

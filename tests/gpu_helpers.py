@@ -33,11 +33,13 @@ def boxcar_at(P, i, w):
     return float(np.sum(P[int(i):int(i) + int(w)], dtype=np.float64))
 
 
-def compare_candidates(gpu, orc, P, ntrials, sigma_thresh, oracle_mod, label=""):
+def compare_candidates(gpu, orc, P, ntrials, sigma_thresh, oracle_mod, label="", dofmul=1):
     """Compare GPU candidates with the oracle's SearchResult (tables=True).
 
-    Returns the list of (chunk, width) entries accepted only because they sit
-    within SIGMA_BAND of the threshold.
+    P is the searched series: the power, or harmonic stage H, whose width-w
+    boxcars have 2 w dofmul degrees of freedom with dofmul = H(H+1)/2.
+    Returns the list of (chunk, width) entries accepted only because they
+    sit within SIGMA_BAND of the threshold.
     """
     g = {(int(c["chunk"]), int(c["width"])): c for c in gpu}
     o = {(int(c["chunk"]), int(c["width"])): c for c in orc.cands}
@@ -48,7 +50,7 @@ def compare_candidates(gpu, orc, P, ntrials, sigma_thresh, oracle_mod, label="")
         banded.append(k)
     for k in set(g) - set(o):
         c, w = k
-        s = oracle_mod.candidate_sigma(orc.M[c, w - 1], w, ntrials)
+        s = oracle_mod.candidate_sigma(orc.M[c, w - 1], w * dofmul, ntrials)
         assert abs(s - sigma_thresh) < SIGMA_BAND, f"{label} gpu-only candidate {k} sigma {s}"
         banded.append(k)
     for k in set(g) & set(o):

@@ -58,14 +58,17 @@ def test_struct_layout_matches_binding(tmp_path):
 #include "pulscan.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(pulscan_candidate), sizeof(pulscan_candidates), sizeof(pulscan_opts));
-  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_candidate, spectrum), offsetof(pulscan_candidate, bin),
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_candidate, spectrum), offsetof(pulscan_candidate, bin),
          offsetof(pulscan_candidate, width), offsetof(pulscan_candidate, power),
-         offsetof(pulscan_candidate, sigma), offsetof(pulscan_candidate, chunk));
+         offsetof(pulscan_candidate, sigma), offsetof(pulscan_candidate, chunk),
+         offsetof(pulscan_candidate, harmonics));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(pulscan_candidates, capacity), offsetof(pulscan_candidates, count),
          offsetof(pulscan_candidates, on_device), offsetof(pulscan_candidates, count_device), sizeof(pulscan_complex));
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_opts, norm), offsetof(pulscan_opts, norm_block),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_opts, norm), offsetof(pulscan_opts, norm_block),
          offsetof(pulscan_opts, ntrials), offsetof(pulscan_opts, width_search),
-         offsetof(pulscan_opts, async), offsetof(pulscan_opts, stream), offsetof(pulscan_opts, dense));
+         offsetof(pulscan_opts, async), offsetof(pulscan_opts, stream), offsetof(pulscan_opts, dense),
+         offsetof(pulscan_opts, numharm), offsetof(pulscan_opts, best_per_chunk),
+         offsetof(pulscan_opts, rblock));
   return 0;
 }
 """)
@@ -78,14 +81,17 @@ int main(void) {
                      ctypes.sizeof(pk.pulscan_opts)]
     C = pk.pulscan_candidate
     assert [int(v) for v in lines[1].split()] == [C.spectrum.offset, C.bin.offset, C.width.offset,
-                                                  C.power.offset, C.sigma.offset, C.chunk.offset]
+                                                  C.power.offset, C.sigma.offset, C.chunk.offset,
+                                                  C.harmonics.offset]
     S = pk.pulscan_candidates
     assert [int(v) for v in lines[2].split()] == [S.capacity.offset, S.count.offset,
                                                   S.on_device.offset, S.count_device.offset, 8]
     O = pk.pulscan_opts
     assert [int(v) for v in lines[3].split()] == [O.norm.offset, O.norm_block.offset,
                                                   O.ntrials.offset, O.width_search.offset,
-                                                  O.async_.offset, O.stream.offset, O.dense.offset]
+                                                  O.async_.offset, O.stream.offset, O.dense.offset,
+                                                  O.numharm.offset, O.best_per_chunk.offset,
+                                                  O.rblock.offset]
     assert [d[0] for d in pk.CANDIDATE_DTYPE.descr] == [f[0] for f in C._fields_]
 
 
@@ -96,8 +102,9 @@ def test_strerror_and_default_options(L):
     assert "capacity" in pk.pulscan_strerror(-3)
     assert pk.pulscan_strerror(12345) == "unknown status"
     o = pk.pulscan_opts_default()
-    assert (o.norm, o.norm_block, o.ntrials, o.width_search, o.async_, o.stream, o.dense) == \
-        (pk.PULSCAN_NORM_MOM, 0, 0.0, pk.PULSCAN_W_ALL, 0, None, 0)
+    assert (o.norm, o.norm_block, o.ntrials, o.width_search, o.async_, o.stream, o.dense,
+            o.numharm, o.best_per_chunk, o.rblock) == \
+        (pk.PULSCAN_NORM_MOM, 0, 0.0, pk.PULSCAN_W_ALL, 0, None, 0, 1, 0, 0)
 
 
 def test_null_arguments_are_rejected_without_a_device(L):

@@ -265,7 +265,7 @@ def test_async_device_output(ctx, pk, oracle_lib):
     d = to_device(x)
     ref, n_ref = ctx.pulscan_search_ex(d, wl.zmax, wl.chunk, wl.sigma)
     cap = 4096
-    buf = torch.zeros(cap * 24, dtype=torch.uint8, device="cuda")
+    buf = torch.zeros(cap * pk.CANDIDATE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
     s = torch.cuda.current_stream()
     opts = pk.make_opts(async_=True, stream=s)
@@ -274,7 +274,7 @@ def test_async_device_output(ctx, pk, oracle_lib):
     torch.cuda.synchronize()
     n = int(cnt.item())
     assert n == n_ref
-    got = buf.cpu().numpy()[:n * 24].view(pk.CANDIDATE_DTYPE)
+    got = buf.cpu().numpy()[:n * pk.CANDIDATE_DTYPE.itemsize].view(pk.CANDIDATE_DTYPE)
     assert got.tobytes() == ref.tobytes()
 
 

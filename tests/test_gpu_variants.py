@@ -1,0 +1,171 @@
+"""GPU parity of the search variants: harmonic summing (section 2.3),
+r-block output (section 2.4) and the best candidate per chunk, each through
+the C ABI against the FP64 oracle (or, where the variant only reorganises
+the same candidates, against the library's own plain output)."""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import SIGMA_ATOL, SIGMA_BAND, compare_candidates, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2406_15186_amd as pk
+    pk.lib()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    import torch
+    assert torch.cuda.is_available()
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def stage_parity(ctx, pk, oracle, x, Z, C, sigma, numharm, label, **kw):
+    n = x.shape[0]
+    d = to_device(x)
+    got, cnt = ctx.pulscan_search_ex(d, Z, C, sigma, opts=pk.make_opts(numharm=numharm, **kw))
+    assert cnt == len(got)
+    orc = oracle.search(x, Z, C, sigma, tables=True, numharm=numharm)
+    for H in range(1, numharm + 1):
+        S = orc.P if H == 1 else oracle.harmonic_sum(orc.P, H)
+        M, I = oracle.chunk_maxima(S, Z, C)
+        sub = oracle.SearchResult(orc.cands[orc.cands["harm"] == H], M, I)
+        compare_candidates(got[got["harmonics"] == H], sub, S, float((n // H) * Z), sigma,
+                           oracle, label=f"{label} H={H}", dofmul=H * (H + 1) // 2)
+    keys = [(int(c["harmonics"]), int(c["chunk"]), int(c["width"])) for c in got]
+    assert keys == sorted(keys), f"{label}: not in (stage, chunk, width) order"
+    say(f"{label}: {len(got)} candidates, per stage {np.bincount(got['harmonics'])[1:].tolist()}")
+    return got
+
+
+@pytest.mark.parametrize("nbins,Z,C,numharm", [(1 << 16, 64, 256, 4), ((1 << 16) + 123, 64, 256, 3),
+                                               (1 << 20, 200, 1024, 4), (5000, 16, 64, 8)])
+def test_harmonic_stages_match_oracle(ctx, pk, oracle_lib, nbins, Z, C, numharm):
+    wl = synth.workload("plain_2e16")
+    say(f"harmonics nbins={nbins} Z={Z} C={C} numharm={numharm}")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=nbins)
+    got = stage_parity(ctx, pk, oracle_lib, x, Z, C, wl.sigma, numharm, f"harm n={nbins}")
+    assert len(got) > 0
+
+
+def test_harmonic_pruned_equals_dense(ctx, pk, oracle_lib):
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    d = to_device(x)
+    a, na = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(numharm=4))
+    b, nb = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(numharm=4, dense=True))
+    assert na == nb and (a == b).all()
+
+
+def test_harmonic_batched_equals_plain(ctx, pk, oracle_lib):
+    wl = synth.workload("plain_2e16")
+    xs = [synth.make_spectrum(wl, oracle_lib.power_for_sigma, spawn=s, nbins=n)[0]
+          for s, n in ((0, 1 << 16), (1, 40000), (2, 50001))]
+    ds = [to_device(x) for x in xs]
+    opts = pk.make_opts(numharm=3)
+    got, cnt, used = ctx.pulscan_search_batched(ds, [64, 32, 48], 256, 6.0, opts=opts)
+    assert used == 256 and cnt == len(got)
+    parts = []
+    for s, (d, z) in enumerate(zip(ds, [64, 32, 48])):
+        g, _ = ctx.pulscan_search_ex(d, z, 256, 6.0, opts=opts)
+        g["spectrum"] = s
+        parts.append(g)
+    ref = np.concatenate(parts)
+    assert len(ref) == len(got) and (ref == got).all()
+
+
+def test_rblock_reports_block_indices(ctx, pk, oracle_lib):
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    d = to_device(x)
+    a, _ = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(numharm=2))
+    b, _ = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(numharm=2, rblock=1000))
+    assert len(a) == len(b) > 0
+    np.testing.assert_array_equal(b["bin"], a["bin"] // 1000)
+    for f in ("spectrum", "width", "power", "sigma", "chunk", "harmonics"):
+        np.testing.assert_array_equal(a[f], b[f])
+
+
+def best_of(c):
+    """Per (spectrum, stage, chunk) run of a canonical list: the highest sigma,
+    the first on ties."""
+    out = []
+    i = 0
+    while i < len(c):
+        j = i
+        key = (c[i]["spectrum"], c[i]["harmonics"], c[i]["chunk"])
+        b = i
+        while j < len(c) and (c[j]["spectrum"], c[j]["harmonics"], c[j]["chunk"]) == key:
+            if c[j]["sigma"] > c[b]["sigma"]:
+                b = j
+            j += 1
+        out.append(c[b])
+        i = j
+    return np.array(out, dtype=c.dtype) if out else c[:0]
+
+
+@pytest.mark.parametrize("numharm", [1, 3])
+def test_best_per_chunk(ctx, pk, oracle_lib, numharm):
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    d = to_device(x)
+    full, _ = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(numharm=numharm))
+    best, cnt = ctx.pulscan_search_ex(d, 64, 256, 6.0,
+                                      opts=pk.make_opts(numharm=numharm, best_per_chunk=True))
+    assert cnt == len(best) > 0
+    ref = best_of(full)
+    assert len(ref) == len(best) and (ref == best).all()
+    # against the oracle: each kept chunk's sigma is the oracle's best there
+    orc = oracle_lib.search(x, 64, 256, 6.0, numharm=numharm).cands
+    groups = {}
+    for c in orc:
+        k = (int(c["harm"]), int(c["chunk"]))
+        groups[k] = max(groups.get(k, -np.inf), float(c["sigma"]))
+    kept = {(int(c["harmonics"]), int(c["chunk"])): float(c["sigma"]) for c in best}
+    for k, s in kept.items():
+        if k not in groups:
+            assert abs(s - 6.0) < 10 * SIGMA_BAND, k
+            continue
+        assert abs(s - groups[k]) <= 2 * SIGMA_ATOL, (k, s, groups[k])
+    for k in set(groups) - set(kept):
+        assert abs(groups[k] - 6.0) < SIGMA_BAND, k
+
+
+def test_best_per_chunk_async_device_output(ctx, pk, oracle_lib):
+    import torch
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    d = to_device(x)
+    ref, rc = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(best_per_chunk=True,
+                                                                          numharm=2))
+    cap = pk.worst_count(d.shape[0], 64, 256, 2)
+    buf = torch.zeros(cap * pk.CANDIDATE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        o = pk.make_opts(best_per_chunk=True, numharm=2, async_=True, stream=s)
+        ctx.pulscan_search_ex(d, 64, 256, 6.0, capacity=cap, opts=o, out_device=buf,
+                              count_device=cnt)
+    s.synchronize()
+    n = int(cnt.item())
+    assert n == rc
+    got = buf.cpu().numpy()[:n * pk.CANDIDATE_DTYPE.itemsize].view(pk.CANDIDATE_DTYPE)
+    assert (got == ref).all()
+
+
+def test_variant_options_are_validated(ctx, pk):
+    import torch
+    d = torch.zeros((4096, 2), dtype=torch.float32, device="cuda")
+    for kw in ({"numharm": 17}, {"numharm": -1}, {"rblock": -5}):
+        o = pk.make_opts(**kw)
+        with pytest.raises(pk.PulscanError) as e:
+            ctx.pulscan_search_ex(d, 16, 256, 6.0, opts=o)
+        assert e.value.status == pk.PULSCAN_EINVAL
