@@ -53,6 +53,168 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def batched_leg(ctx, pk, synth, args, stream, tone_power):
+    """DM-trial batch: spectra of 2^20..2^23 bins (uniform), zmax in {64, 128,
+    200}, 0-5 tones each, generated on the device.  One fused launch per
+    batch, the chunk and tile picked by the autotuner on the first call, then
+    replayed from a captured graph; compared with one launch per spectrum at
+    the same chunk on the same stream."""
+    import torch
+    wls = synth.batched_workload(nspec=args.batch_spectra)
+    log(f"bench: batched leg, {len(wls)} spectra")
+    xs = []
+    for w in wls:
+        x, _ = synth.make_spectrum_device(w, tone_power)
+        xs.append(x)
+    torch.cuda.synchronize()
+    zs = [w.zmax for w in wls]
+    nb = sum(w.nbins for w in wls)
+    bw = sum(w.nbins * w.zmax for w in wls)
+    cap = 1 << 22
+    buf = torch.empty(cap * pk.CANDIDATE_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    t0 = time.perf_counter()
+    _, n0, chunk = ctx.pulscan_search_batched(xs, zs, 0, 6.0, capacity=cap, out_device=buf,
+                                              count_device=cnt)
+    tune_s = time.perf_counter() - t0
+    log(f"bench: autotuned chunk {chunk} in {tune_s:.2f} s; {n0} candidates per batch")
+    opts = pk.make_opts(async_=True, stream=stream, graph=True)
+
+    def batch():
+        ctx.pulscan_search_batched(xs, zs, chunk, 6.0, capacity=cap, opts=opts, out_device=buf,
+                                   count_device=cnt)
+
+    batch()   # direct run, then capture
+    batch()   # first replay
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.batch_steps):
+        batch()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.batch_steps
+    assert int(cnt.item()) == n0, "graph replays disagree with the direct batched call"
+
+    # the same spectra one launch each
+    popts = pk.make_opts(async_=True, stream=stream)
+    pbuf = torch.empty((1 << 16) * pk.CANDIDATE_DTYPE.itemsize, dtype=torch.uint8,
+                       device="cuda:0")
+    pcnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+
+    def plain_all():
+        for x, z in zip(xs, zs):
+            ctx.pulscan_search_ex(x, z, chunk, 6.0, capacity=1 << 16, opts=popts, out_device=pbuf,
+                                  count_device=pcnt)
+
+    plain_all()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    plain_all()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    pms = ev0.elapsed_time(ev1)
+    log(f"bench: batched {ms:.3f} ms per batch (graph), plain {pms:.3f} ms for the same spectra")
+    del xs
+    torch.cuda.empty_cache()
+    return {"workload": f"dm_trials_{len(wls)}", "spectra": len(wls), "bins": nb,
+            "bin_widths": bw, "value": round(bw / (ms * 1e-3) / 1e9, 3),
+            "unit": "G bin-widths/s", "ms_per_batch": round(ms, 4),
+            "hbm_frac": round(8.0 * nb / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "chunk": chunk, "graph": True, "candidates": n0,
+            "plain_value": round(bw / (pms * 1e-3) / 1e9, 3), "plain_ms": round(pms, 4),
+            "speedup_vs_plain": round(pms / ms, 3), "autotune_s": round(tune_s, 2)}
+
+
+def serve_stream(pk, pool, rate, seconds, host, max_batch, seed):
+    """Poisson arrivals at `rate` per second for `seconds`, each a spectrum
+    drawn from `pool` (device tensors, or pinned host pointers if `host`);
+    returns (completed, bin-widths, wall seconds, latencies in ms, launches)."""
+    import threading
+    srv = pk.Server(0, hbm_budget=4 << 30, max_batch=max_batch, chunk=1024, sigma_thresh=6.0)
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.5) + 16)
+    picks = rng.integers(0, len(pool), size=gaps.size)
+    sent = []
+
+    def feeder():
+        t = time.perf_counter()
+        t_end = t + seconds
+        nxt = t
+        for g, k in zip(gaps, picks):
+            nxt += g
+            if nxt > t_end:
+                break
+            d = nxt - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ptr, n, z = pool[k]
+            srv.pulscan_server_submit(ptr, n, z, not host)
+            sent.append(n * z)
+
+    th = threading.Thread(target=feeder)
+    t0 = time.perf_counter()
+    th.start()
+    lat = []
+    work = 0
+    while th.is_alive() or len(lat) < len(sent):
+        for (tk, status, total, ts, tb, td, c) in srv.pulscan_server_poll(wait_ms=20):
+            assert status == pk.PULSCAN_OK, status
+            lat.append((td - ts) * 1e3)
+    wall = time.perf_counter() - t0
+    th.join()
+    launches = srv.pulscan_server_stats()[2]
+    srv.close()
+    work = sum(sent)
+    return len(lat), work, wall, np.array(lat), launches
+
+
+def serving_leg(pk, synth, args, tone_power):
+    """Serving stream: Poisson arrivals at 200 spectra/s of 2^21..2^23 bins,
+    zmax 200, chunk 1024, a 4 GiB device admission budget; device-resident
+    spectra (the paper's timing excludes transfers) for the main figure, then
+    pinned host spectra copied by the server, and the same arrivals served
+    one launch per spectrum (max_batch 1) for comparison."""
+    import torch
+    rng = np.random.default_rng(4)
+    pool, host_pool, hosts = [], [], []
+    for k in range(32):
+        n = int(rng.integers(1 << 21, (1 << 23) + 1))
+        w = synth.Workload(f"serve_{k}", n, 200, 1024, 6.0, 4 * 1000003 + k, int(rng.integers(0, 6)),
+                           None, (1, 200), (5.0, 20.0), (1000, n - 202))
+        x, _ = synth.make_spectrum_device(w, tone_power)
+        pool.append((x, n, 200))
+        hp = pk.pulscan_host_alloc(n * 8)
+        hosts.append(hp)
+        torch.cuda.synchronize()
+        import ctypes
+        ctypes.memmove(hp, x.cpu().numpy().ctypes.data, n * 8)
+        host_pool.append((hp, n, 200))
+    dev_pool = [(x.data_ptr(), n, z) for x, n, z in pool]
+    out = {}
+    for name, p, host, secs, mb in (("device", dev_pool, False, args.serve_seconds, 256),
+                                    ("host", host_pool, True, min(10.0, args.serve_seconds), 256),
+                                    ("device_plain", dev_pool, False, min(10.0, args.serve_seconds), 1)):
+        log(f"bench: serving leg {name}, {secs:.0f} s at {args.serve_rate:.0f}/s")
+        done, work, wall, lat, launches = serve_stream(pk, p, args.serve_rate, secs, host, mb,
+                                                       seed=4)
+        out[name] = {"completed": done, "seconds": round(wall, 2),
+                     "value": round(work / wall / 1e9, 3), "unit": "G bin-widths/s",
+                     "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                     "launches": launches, "max_batch": mb}
+        log(f"bench: {name}: {done} spectra, p50 {out[name]['p50_ms']} ms, "
+            f"p99 {out[name]['p99_ms']} ms, {launches} launches")
+    for hp in hosts:
+        pk.pulscan_host_free(hp)
+    del pool
+    torch.cuda.empty_cache()
+    out["arrivals_per_s"] = args.serve_rate
+    out["workload"] = "poisson_2e21_2e23_z200"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +225,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dense", action="store_true",
                     help="evaluate every width block (no pruning bound): same candidates")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched DM-trial leg (512 spectra of 2^20..2^23 bins)")
+    ap.add_argument("--batch-spectra", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="duration of the Poisson arrival stream (device-resident spectra); "
+                         "0 skips the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-reference-mib", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB once on the device, so "
                          "that hardware byte counters can be scaled by a copy of known size")
@@ -177,6 +347,14 @@ def main():
                          f"({dt:.2f} s wall)",
                "candidates": int(len(r.cands))}
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(ctx, pk, synth, args, stream, tone_power)
+
+    served = None
+    if args.serve_seconds > 0:
+        served = serving_leg(pk, synth, args, tone_power)
+
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "G bin-widths/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
@@ -192,6 +370,8 @@ def main():
         "plain_sync_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                                   "p99": round(float(np.percentile(lat, 99)), 4)},
         "candidates_per_step": ref_count,
+        "batched": batched,
+        "served": served,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

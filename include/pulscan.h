@@ -132,6 +132,19 @@ typedef struct {
                            of chunks kept                                          */
   int32_t rblock;       /* > 0: candidates report the r-block index bin / rblock in
                            place of the bin (section 2.4); 0 = exact bins         */
+  int32_t graph;        /* 1: the context captures the call's launches in a HIP
+                           graph and replays it for later calls with the same
+                           arguments (spectra, sizes, options, output buffers);
+                           a call with other arguments recaptures.  The first
+                           call of a set runs directly                           */
+  int32_t power_fp16;   /* 1: the bank keeps normalised power in FP16 (FP32 sums):
+                           half the LDS, more workgroups per CU.  It compares
+                           against thresholds 0.5 sigma lower, and every
+                           candidate within 0.5 sigma of the threshold is
+                           re-decided on its FP32 power, recomputed from the
+                           spectrum; other candidates report FP16-based power
+                           (relative error up to about 5e-4).  Not with 4096-bin
+                           normalisation blocks                                  */
 } pulscan_opts;
 
 typedef struct pulscan_ctx pulscan_ctx;
@@ -218,6 +231,74 @@ int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, doub
  * their number, and clears the record. */
 int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable);
 int pulscan_ctx_kernel_time(pulscan_ctx *ctx, double *total_ms, uint64_t *launches);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: spectra searched as they arrive.                                */
+/* ---------------------------------------------------------------------- */
+
+/* A server owns a context, two streams (copies and searches), a device ring
+ * of hbm_budget bytes for copies of host spectra, and a worker thread.  The
+ * worker admits submitted spectra in arrival order while the bytes of the
+ * admitted, unfinished spectra stay within hbm_budget (a spectrum larger
+ * than what is free waits; one alone is always admitted), searches each
+ * admitted set (at most max_batch spectra) in one batched launch while the
+ * next set is being copied, and publishes every spectrum's candidates with
+ * its timestamps. */
+typedef struct pulscan_server pulscan_server;
+
+typedef struct {
+  uint64_t hbm_budget;     /* bytes of spectra in flight (default 4 GiB)              */
+  int32_t max_batch;       /* spectra per launch (default 256)                        */
+  int32_t chunk;           /* chunk of every search (default 1024)                    */
+  float sigma_thresh;      /* default 6                                               */
+  uint32_t max_candidates; /* per launch; further candidates are counted, dropped
+                              and flagged PULSCAN_EOVERFLOW (default 2^20)            */
+  pulscan_opts opts;       /* search options (async, graph and stream must be 0)     */
+} pulscan_server_config;
+
+typedef struct {
+  int64_t ticket;          /* as returned by pulscan_server_submit                   */
+  int32_t status;          /* PULSCAN_OK or the search's error                       */
+  uint32_t count;          /* candidates in `candidates`                             */
+  uint64_t total;          /* candidates found                                       */
+  double t_submit;         /* seconds on the server's clock: submitted,              */
+  double t_start;          /*   admitted (its set's launch queued),                  */
+  double t_done;           /*   results on the host                                  */
+  const pulscan_candidate *candidates; /* host, owned by the server, valid until
+                              the next pulscan_server_poll; spectrum = 0          */
+} pulscan_result;
+
+/* Defaults as listed in pulscan_server_config. */
+void pulscan_server_config_default(pulscan_server_config *cfg);
+
+/* Create a server on `device`; EINVAL for bad settings, ENOMEM if its device
+ * memory cannot be allocated. */
+int pulscan_server_create(pulscan_server **srv, int device, const pulscan_server_config *cfg);
+
+/* Finish every submitted spectrum, stop the worker and free everything. */
+void pulscan_server_destroy(pulscan_server *srv);
+
+/* Queue one spectrum of nbins complex amplitudes and widths 1..zmax.
+ * on_device = 0: host memory, copied by the server (pinned memory from
+ * pulscan_host_alloc copies fastest); 1: device memory, searched in place.
+ * The memory must stay valid and unchanged until the result is polled.
+ * Returns the ticket (>= 0) or a negative pulscan_status.  Invalid
+ * spectra (too short for the chunk, ...) are reported in their result. */
+int64_t pulscan_server_submit(pulscan_server *srv, const pulscan_complex *spectrum,
+                              uint64_t nbins, int32_t zmax, int32_t on_device);
+
+/* Take up to max_results finished results, oldest first, waiting up to
+ * wait_ms for the first one.  Returns how many were written. */
+int pulscan_server_poll(pulscan_server *srv, pulscan_result *results, int max_results,
+                        int wait_ms);
+
+/* Spectra waiting, finished so far, launches made, bytes admitted now. */
+int pulscan_server_stats(pulscan_server *srv, uint64_t *pending, uint64_t *completed,
+                         uint64_t *batches, uint64_t *budget_used);
+
+/* Pinned host memory for spectra (hipHostMalloc); free with pulscan_host_free. */
+int pulscan_host_alloc(void **ptr, uint64_t bytes);
+void pulscan_host_free(void *ptr);
 
 #ifdef __cplusplus
 }

@@ -54,12 +54,28 @@ class pulscan_opts(ctypes.Structure):
                 ("ntrials", ctypes.c_double), ("width_search", ctypes.c_int32),
                 ("async_", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("dense", ctypes.c_int32), ("numharm", ctypes.c_int32),
-                ("best_per_chunk", ctypes.c_int32), ("rblock", ctypes.c_int32)]
+                ("best_per_chunk", ctypes.c_int32), ("rblock", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("power_fp16", ctypes.c_int32)]
 
 
+class pulscan_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("sigma_thresh", ctypes.c_float),
+                ("max_candidates", ctypes.c_uint32), ("opts", pulscan_opts)]
+
+
+class pulscan_result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("count", ctypes.c_uint32), ("total", ctypes.c_uint64),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("candidates", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(pulscan_server_config) == 80
+assert ctypes.sizeof(pulscan_result) == 56
 assert ctypes.sizeof(pulscan_candidate) == 32 == CANDIDATE_DTYPE.itemsize
 assert ctypes.sizeof(pulscan_candidates) == 40
-assert ctypes.sizeof(pulscan_opts) == 48
+assert ctypes.sizeof(pulscan_opts) == 56
 
 # every function the header declares: name -> (restype, argtypes)
 _vp, _sz, _i, _f, _d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float, ctypes.c_double
@@ -81,6 +97,15 @@ SIGNATURES = {
     "pulscan_threshold_table": (_i, [_vp, _i, _f, _d, _i, ctypes.POINTER(ctypes.c_float)]),
     "pulscan_ctx_set_timing": (_i, [_vp, _i]),
     "pulscan_ctx_kernel_time": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint64)]),
+    "pulscan_server_config_default": (None, [ctypes.POINTER(pulscan_server_config)]),
+    "pulscan_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(pulscan_server_config)]),
+    "pulscan_server_destroy": (None, [_vp]),
+    "pulscan_server_submit": (ctypes.c_int64, [_vp, _vp, ctypes.c_uint64, ctypes.c_int32,
+                                               ctypes.c_int32]),
+    "pulscan_server_poll": (_i, [_vp, ctypes.POINTER(pulscan_result), _i, _i]),
+    "pulscan_server_stats": (_i, [_vp] + [ctypes.POINTER(ctypes.c_uint64)] * 4),
+    "pulscan_host_alloc": (_i, [ctypes.POINTER(_vp), ctypes.c_uint64]),
+    "pulscan_host_free": (None, [_vp]),
 }
 
 _lib = None
@@ -153,11 +178,13 @@ def worst_count(nbins: int, zmax: int, chunk: int, numharm: int = 1) -> int:
 def make_opts(norm: int = PULSCAN_NORM_MOM, norm_block: int = 0, ntrials: float = 0.0,
               width_search: int = PULSCAN_W_ALL, async_: bool = False, stream=None,
               dense: bool = False, numharm: int = 1, best_per_chunk: bool = False,
-              rblock: int = 0) -> pulscan_opts:
+              rblock: int = 0, graph: bool = False, power_fp16: bool = False) -> pulscan_opts:
     o = pulscan_opts_default()
     o.norm, o.norm_block, o.ntrials = norm, norm_block, ntrials
     o.width_search, o.async_, o.dense = width_search, int(bool(async_)), int(bool(dense))
     o.numharm, o.best_per_chunk, o.rblock = int(numharm), int(bool(best_per_chunk)), int(rblock)
+    o.graph = int(bool(graph))
+    o.power_fp16 = int(bool(power_fp16))
     if stream is not None:
         o.stream = stream if isinstance(stream, int) else stream.cuda_stream
     return o
@@ -315,6 +342,72 @@ class Context:
         _check(lib().pulscan_ctx_kernel_time(self._ctx, ctypes.byref(ms), ctypes.byref(k)),
                "pulscan_ctx_kernel_time")
         return ms.value, k.value
+
+
+class Server:
+    """The serving runtime (``pulscan_server``): submit spectra as they arrive,
+    poll finished results with their timestamps."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 4 << 30, max_batch: int = 256,
+                 chunk: int = 1024, sigma_thresh: float = 6.0, max_candidates: int = 1 << 20,
+                 opts: Optional[pulscan_opts] = None):
+        cfg = pulscan_server_config()
+        lib().pulscan_server_config_default(ctypes.byref(cfg))
+        cfg.hbm_budget, cfg.max_batch, cfg.chunk = hbm_budget, max_batch, chunk
+        cfg.sigma_thresh, cfg.max_candidates = sigma_thresh, max_candidates
+        if opts is not None:
+            cfg.opts = opts
+        self._srv = ctypes.c_void_p()
+        _check(lib().pulscan_server_create(ctypes.byref(self._srv), device, ctypes.byref(cfg)),
+               "pulscan_server_create")
+        self._res = (pulscan_result * 1024)()
+
+    def close(self):
+        if self._srv:
+            lib().pulscan_server_destroy(self._srv)
+            self._srv = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pulscan_server_submit(self, ptr: int, nbins: int, zmax: int, on_device: bool) -> int:
+        """Queue a spectrum by address (device pointer, or pinned/host pointer)."""
+        t = lib().pulscan_server_submit(self._srv, ptr, nbins, zmax, int(bool(on_device)))
+        if t < 0:
+            raise PulscanError(int(t), "pulscan_server_submit")
+        return int(t)
+
+    def pulscan_server_poll(self, wait_ms: int = 0, max_results: int = 1024):
+        """Finished results: list of (ticket, status, total, t_submit, t_start,
+        t_done, candidates array)."""
+        k = lib().pulscan_server_poll(self._srv, self._res, min(max_results, 1024), wait_ms)
+        _check(k if k < 0 else 0, "pulscan_server_poll")
+        out = []
+        for r in self._res[:k]:
+            c = np.zeros(r.count, dtype=CANDIDATE_DTYPE)
+            if r.count:
+                ctypes.memmove(c.ctypes.data, r.candidates, r.count * CANDIDATE_DTYPE.itemsize)
+            out.append((r.ticket, r.status, r.total, r.t_submit, r.t_start, r.t_done, c))
+        return out
+
+    def pulscan_server_stats(self):
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().pulscan_server_stats(self._srv, *[ctypes.byref(x) for x in v]),
+               "pulscan_server_stats")
+        return tuple(int(x.value) for x in v)
+
+
+def pulscan_host_alloc(nbytes: int) -> int:
+    p = ctypes.c_void_p()
+    _check(lib().pulscan_host_alloc(ctypes.byref(p), nbytes), "pulscan_host_alloc")
+    return int(p.value)
+
+
+def pulscan_host_free(ptr: int) -> None:
+    lib().pulscan_host_free(ctypes.c_void_p(ptr))
 
 
 def pulscan_search(spectrum, zmax: int, chunk: int, sigma_thresh: float,

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libpulscan.so")
-SOURCES = ["api.hip", "bank.hip", "signif.hip", "harmonic.hip"]
+SOURCES = ["api.hip", "bank.hip", "signif.hip", "harmonic.hip", "serve.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

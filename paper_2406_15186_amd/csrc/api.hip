@@ -39,8 +39,24 @@ struct pulscan_ctx {
   int device = 0;
   DevBuf thr, pool, tile_word, tile_prefix, counters, outbuf, descs, jobs;
   DevBuf allbuf, hpow, hsum, hjobs;  // best-per-chunk scratch; harmonic power, sums, jobs
-  uint32_t gen = 0;  // launch generation of the per-tile count words
+  DevBuf tune_out;                   // autotuner: candidate output of its timing runs
+  DevBuf stats;                      // FP16 search: per-block statistics for the re-check
   ThrKey thr_key;
+  // what the device holds for batched launches (re-uploaded only on change)
+  std::vector<ThreshJob> last_jobs;
+  float last_sigma = 0.f;
+  int last_ws = -1, last_debug = -1;
+  std::vector<HarmJob> last_hjobs;
+  // autotuner: (batch signature) -> (chunk, tile)
+  std::vector<std::pair<std::vector<uint64_t>, std::pair<uint32_t, uint32_t>>> tuned;
+  // graph replay of the last graph-mode call
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint64_t> graph_key;
+  // bumped whenever device memory a captured graph may use is reallocated or
+  // refilled with other contents (thresholds, descriptors, stage jobs)
+  uint64_t epoch = 0;
+  uint64_t graph_epoch = 0;
   // pinned staging of batched descriptors / threshold jobs
   void *pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -63,8 +79,8 @@ struct Counters {
   uint32_t overflow;
   uint32_t head;
   uint32_t done;
-  uint32_t pad;
-  unsigned long long best;  // candidates kept by the best-per-chunk pass
+  uint32_t gen;             // generation tag of the last launch's tile words
+  unsigned long long best;  // candidates kept by the final pass (best / re-check)
 };
 
 #define HIP_TRY(call)                       \
@@ -79,8 +95,8 @@ int grow(pulscan_ctx *ctx, DevBuf &b, size_t bytes, bool zero) {
   if (bytes == 0) bytes = 8;
   if (b.bytes >= bytes) return PULSCAN_OK;
   // a buffer may still be read by work queued earlier on any stream
-  (void)ctx;
   HIP_TRY(hipDeviceSynchronize());
+  ++ctx->epoch;
   if (b.p) {
     HIP_TRY(hipFree(b.p));
     b.p = nullptr;
@@ -122,6 +138,7 @@ int grow_pinned(pulscan_ctx *ctx, size_t bytes) {
 // Copy host bytes to device through the pinned staging buffer; the buffer is
 // reused only after the copy has completed (an event guards it).
 int upload(pulscan_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t stream) {
+  ++ctx->epoch;
   int st = grow_pinned(ctx, bytes);
   if (st) return st;
   memcpy(ctx->pinned, src, bytes);
@@ -156,11 +173,14 @@ int check_spectrum(const void *x, uint64_t n, int zmax, int chunk, const pulscan
   if (o.numharm < 0 || o.numharm > kMaxHarm) return PULSCAN_EINVAL;
   if (o.best_per_chunk != 0 && o.best_per_chunk != 1) return PULSCAN_EINVAL;
   if (o.rblock < 0) return PULSCAN_EINVAL;
+  if (o.graph != 0 && o.graph != 1) return PULSCAN_EINVAL;
+  if (o.power_fp16 != 0 && o.power_fp16 != 1) return PULSCAN_EINVAL;
   const uint64_t B = o.norm_block > 0 ? (uint64_t)o.norm_block : (uint64_t)chunk;
   if (n < B || n < (uint64_t)zmax) return PULSCAN_EINVAL;
   if (o.norm == PULSCAN_NORM_MOM && !is_pow4(B)) return PULSCAN_EINVAL;
   if (o.norm == PULSCAN_NORM_EXACT) return PULSCAN_EUNSUPPORTED;
   if (B < 64 || B > 4096) return PULSCAN_EUNSUPPORTED;
+  if (o.power_fp16 && B == 4096) return PULSCAN_EUNSUPPORTED;
   if (chunk % 64 != 0 || chunk > kMaxTile) return PULSCAN_EUNSUPPORTED;
   const uint64_t nchunks = (n + chunk - 1) / chunk;
   if (nchunks * (uint64_t)zmax >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
@@ -205,6 +225,7 @@ struct RunArgs {
   RunKind kind = kRunSearch;
   bool from_power = false;  // the series are float power (no normalisation)
   uint32_t chunk = 0, block = 0;
+  uint32_t tile = 0;        // 0: the heuristic tile; else the autotuner's
   float sigma = 0.f;
   pulscan_opts opts{};
   pulscan_candidates *out = nullptr;
@@ -214,10 +235,19 @@ struct RunArgs {
   float *stats_out = nullptr;
 };
 
-// One fused launch of the bank kernel over a batch of series, then (search
-// mode) the emission of the candidates and, on request, the best-per-chunk
-// pass.
-int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
+// What a synchronous search reads back once its launches are queued.
+struct Pending {
+  Counters *cnt = nullptr;
+  bool best = false;     // the count comes from the final pass
+  uint64_t cap = 0;      // entries of the destination the caller receives
+  bool host = false;     // results go through ctx->outbuf to host memory
+};
+
+// Queue one fused launch of the bank kernel over a batch of series and, in
+// search mode, the emission of the candidates and the best-per-chunk pass.
+// Never waits on the device except to grow a buffer (which a call repeating
+// an earlier one never does), so it can run under stream capture.
+int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a, Pending *pend) {
   hipStream_t stream = (hipStream_t)a.opts.stream;
   const int nspec = (int)specs.size();
   const bool search = a.kind == kRunSearch;
@@ -230,8 +260,19 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
     zmax_max = s.zmax > zmax_max ? s.zmax : zmax_max;
     n_min = s.n < n_min ? s.n : n_min;
   }
+  const bool fp16 = search && a.opts.power_fp16;
   Geometry g;
-  if (!choose_geometry(a.chunk, a.block, zmax_max, n_min, &g)) return PULSCAN_EUNSUPPORTED;
+  if (!choose_geometry(a.chunk, a.block, zmax_max, n_min, &g, a.tile, fp16))
+    return PULSCAN_EUNSUPPORTED;
+  // FP16 search on spectra: room for every block's statistics
+  float *stats = nullptr;
+  if (fp16 && !a.from_power) {
+    uint64_t nb = 0;
+    for (const SpecIn &s : specs) nb += (s.n + a.block - 1) / a.block;
+    int st0 = grow(ctx, ctx->stats, nb * 4 * sizeof(float), false);
+    if (st0) return st0;
+    stats = static_cast<float *>(ctx->stats.p);
+  }
 
   // descriptors
   std::vector<SpecDesc> descs(nspec);
@@ -242,6 +283,10 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
     d = SpecDesc{};
     d.x = reinterpret_cast<const float2 *>(specs[s].x);
     d.aux = specs[s].aux;
+    if (stats) {
+      d.aux = stats;
+      stats += 4 * ((specs[s].n + a.block - 1) / a.block);
+    }
     d.n = (uint32_t)specs[s].n;
     d.zmax = specs[s].zmax;
     d.zc = round_widths(d.zmax, g.K);
@@ -260,28 +305,27 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
     zc_max = d.zc > zc_max ? d.zc : zc_max;
   }
 
-  // thresholds: table s at thr + s * zc_max
+  // thresholds: table s at thr + s * zc_max, recomputed only when the batch's
+  // (zmax, ntrials, degrees of freedom) or sigma change
   int st = PULSCAN_OK;
   if (!power_only) {
     const void *thr_before = ctx->thr.p;
     st = grow(ctx, ctx->thr, (size_t)nspec * zc_max * sizeof(float), false);
     if (st) return st;
-    if (ctx->thr.p != thr_before) ctx->thr_key.valid = false;
+    if (ctx->thr.p != thr_before) ctx->last_jobs.clear();
     float *thr = static_cast<float *>(ctx->thr.p);
     for (int s = 0; s < nspec; ++s) descs[s].thr = thr + (size_t)s * zc_max;
-    ThrKey key;
-    key.valid = nspec == 1 && descs[0].dofmul == 1;
-    key.zmax = descs[0].zmax;
-    key.zc = descs[0].zc;
-    key.sigma = a.sigma;
-    key.ntrials = descs[0].ntrials;
-    key.width_search = ws;
-    key.debug = search ? 0 : 1;
-    if (!(key.valid && key == ctx->thr_key)) {
-      std::vector<ThreshJob> jobs(nspec);
-      for (int s = 0; s < nspec; ++s)
-        jobs[s] = ThreshJob{const_cast<float *>(descs[s].thr), descs[s].zmax, descs[s].zc,
-                            descs[s].ntrials, descs[s].dofmul, 0u};
+    std::vector<ThreshJob> jobs(nspec);
+    for (int s = 0; s < nspec; ++s)
+      jobs[s] = ThreshJob{const_cast<float *>(descs[s].thr), descs[s].zmax, descs[s].zc,
+                          descs[s].ntrials, descs[s].dofmul, 0u};
+    const int debug = search ? 0 : 1;
+    // the FP16-stored search compares against thresholds kRecheckBand lower
+    const float tsig = fp16 ? a.sigma - kRecheckBand : a.sigma;
+    const bool same = ctx->last_jobs.size() == jobs.size() && ctx->last_sigma == tsig &&
+                      ctx->last_ws == ws && ctx->last_debug == debug &&
+                      memcmp(ctx->last_jobs.data(), jobs.data(), jobs.size() * sizeof(ThreshJob)) == 0;
+    if (!same) {
       const ThreshJob *jobs_dev = nullptr;
       if (nspec > 1) {
         st = grow(ctx, ctx->jobs, jobs.size() * sizeof(ThreshJob), false);
@@ -290,9 +334,13 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
         if (st) return st;
         jobs_dev = static_cast<const ThreshJob *>(ctx->jobs.p);
       }
-      HIP_TRY(launch_thresholds(jobs_dev, jobs[0], nspec, zc_max, (double)a.sigma, ws, key.debug,
+      HIP_TRY(launch_thresholds(jobs_dev, jobs[0], nspec, zc_max, (double)tsig, ws, debug,
                                 stream));
-      ctx->thr_key = key.valid ? key : ThrKey{};
+      ++ctx->epoch;
+      ctx->last_jobs = jobs;
+      ctx->last_sigma = tsig;
+      ctx->last_ws = ws;
+      ctx->last_debug = debug;
     }
   }
 
@@ -320,6 +368,7 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
   if (worst >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
   const uint32_t pool_cap = (uint32_t)(worst < (uint64_t)kPoolMax ? (worst ? worst : 1) : kPoolMax);
   const bool best = search && a.opts.best_per_chunk;
+  const bool fin = best || fp16;  // a final pass compacts the emitted list
   Counters *cnt = nullptr;
   if (search) {
     st = grow(ctx, ctx->pool, (size_t)pool_cap * sizeof(StageEntry), false);
@@ -336,11 +385,10 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
     bp.pool_head = &cnt->head;
     bp.done = &cnt->done;
     bp.tile_word = static_cast<unsigned long long *>(ctx->tile_word.p);
-    if (++ctx->gen == 0) ctx->gen = 1;  // words start at generation 0
-    bp.gen = ctx->gen;
+    bp.gen = &cnt->gen;
     bp.tile_prefix = static_cast<uint32_t *>(ctx->tile_prefix.p);
     bp.total = &cnt->total;
-    bp.total2 = best ? nullptr : reinterpret_cast<unsigned long long *>(a.out->count_device);
+    bp.total2 = fin ? nullptr : reinterpret_cast<unsigned long long *>(a.out->count_device);
     bp.overflow = &cnt->overflow;
   }
 
@@ -358,7 +406,7 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
   }
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->timing && !power_only) {
+  if (ctx->timing && !power_only && stream != ctx->cap_stream) {
     e0 = take_event(ctx);
     e1 = take_event(ctx);
     if (!e0 || !e1) return PULSCAN_EHIP;
@@ -369,12 +417,7 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
     HIP_TRY(hipEventRecord(e1, stream));
     ctx->ev_rec.emplace_back(e0, e1);
   }
-
-  if (power_only) return PULSCAN_OK;  // ordered before the caller's next launch
-  if (!search) {
-    HIP_TRY(hipStreamSynchronize(stream));
-    return PULSCAN_OK;
-  }
+  if (!search) return PULSCAN_OK;
 
   // emit into the caller's device buffer, or into ours for a host copy; with
   // best_per_chunk everything goes to scratch first
@@ -398,7 +441,11 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
   ep.rblock = (uint32_t)a.opts.rblock;
   ep.out = dst;
   ep.capacity = cap;
-  if (best) {
+  ep.fp16 = fp16 ? 1 : 0;
+  ep.from_power = a.from_power ? 1 : 0;
+  ep.block = a.block;
+  ep.sigma = a.sigma;
+  if (fin) {
     st = grow(ctx, ctx->allbuf, (size_t)pool_cap * sizeof(pulscan_candidate), false);
     if (st) return st;
     ep.out = static_cast<pulscan_candidate *>(ctx->allbuf.p);
@@ -407,21 +454,32 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
   const uint64_t work = ep.capacity < worst ? ep.capacity : worst;
   const uint32_t egrid = (uint32_t)(work / 256 + 1 < 512 ? work / 256 + 1 : 512);
   HIP_TRY(launch_emit(ep, descs[0], egrid, stream));
-  if (best)
-    HIP_TRY(launch_best(ep.out, bp.total, pool_cap, dst, cap, &cnt->best,
-                        reinterpret_cast<unsigned long long *>(out->count_device), stream));
+  if (fin)
+    HIP_TRY(launch_finalize(ep.out, bp.total, pool_cap, dst, cap, &cnt->best,
+                            reinterpret_cast<unsigned long long *>(out->count_device),
+                            best ? 1 : 0, stream));
+  if (pend) {
+    pend->cnt = cnt;
+    pend->best = fin;
+    pend->cap = cap;
+    pend->host = !out->on_device;
+  }
+  return PULSCAN_OK;
+}
 
-  if (a.opts.async) return PULSCAN_OK;
-
+// Wait for a queued search and deliver its count (and host copy).
+int finish(pulscan_ctx *ctx, const RunArgs &a, const Pending &pd) {
+  hipStream_t stream = (hipStream_t)a.opts.stream;
+  pulscan_candidates *out = a.out;
   Counters hc{};
-  HIP_TRY(hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&hc, pd.cnt, sizeof(hc), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   if (hc.overflow == 2) return PULSCAN_EHIP;  // a tile's count never arrived
   if (hc.overflow) return PULSCAN_ENOMEM;
-  const unsigned long long total = best ? hc.best : hc.total;
+  const unsigned long long total = pd.best ? hc.best : hc.total;
   out->count = total;
-  if (!out->on_device) {
-    const uint64_t ncopy = total < cap ? total : cap;
+  if (pd.host) {
+    const uint64_t ncopy = total < pd.cap ? total : pd.cap;
     if (ncopy) {
       HIP_TRY(hipMemcpyAsync(out->data, ctx->outbuf.p, ncopy * sizeof(pulscan_candidate),
                              hipMemcpyDeviceToHost, stream));
@@ -435,7 +493,8 @@ int run_core(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
 // stages 2..numharm are built from it, and all stages of all spectra are
 // searched in one fused launch (power input), stage by stage in canonical
 // order.
-int run_harmonics(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
+int enqueue_harmonics(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a,
+                      Pending *pend) {
   hipStream_t stream = (hipStream_t)a.opts.stream;
   const uint32_t nh = (uint32_t)a.opts.numharm;
   const int nspec = (int)specs.size();
@@ -465,16 +524,21 @@ int run_harmonics(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunA
   }
   RunArgs ap = a;
   ap.kind = kRunPower;
-  st = run_core(ctx, ps, ap);
+  st = enqueue(ctx, ps, ap, nullptr);
   if (st) return st;
 
   // 2. stages 2..numharm
   const HarmJob *jobs_dev = nullptr;
   if (nspec > 1) {
-    st = grow(ctx, ctx->hjobs, jobs.size() * sizeof(HarmJob), false);
-    if (st) return st;
-    st = upload(ctx, ctx->hjobs.p, jobs.data(), jobs.size() * sizeof(HarmJob), stream);
-    if (st) return st;
+    const bool same = ctx->last_hjobs.size() == jobs.size() &&
+                      memcmp(ctx->last_hjobs.data(), jobs.data(), jobs.size() * sizeof(HarmJob)) == 0;
+    if (!same) {
+      st = grow(ctx, ctx->hjobs, jobs.size() * sizeof(HarmJob), false);
+      if (st) return st;
+      st = upload(ctx, ctx->hjobs.p, jobs.data(), jobs.size() * sizeof(HarmJob), stream);
+      if (st) return st;
+      ctx->last_hjobs = jobs;
+    }
     jobs_dev = static_cast<const HarmJob *>(ctx->hjobs.p);
   }
   HIP_TRY(launch_harmonics(jobs_dev, jobs[0], nspec, n_max, stream));
@@ -498,14 +562,208 @@ int run_harmonics(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunA
   }
   RunArgs as = a;
   as.from_power = true;
-  return run_core(ctx, stages, as);
+  return enqueue(ctx, stages, as, pend);
+}
+
+int enqueue_any(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a,
+                Pending *pend) {
+  if (a.kind == kRunSearch && a.opts.numharm > 1) return enqueue_harmonics(ctx, specs, a, pend);
+  return enqueue(ctx, specs, a, pend);
+}
+
+// Graph-mode key: everything a replay bakes in.
+std::vector<uint64_t> graph_key_of(const std::vector<SpecIn> &specs, const RunArgs &a) {
+  std::vector<uint64_t> k;
+  k.push_back(specs.size());
+  for (const SpecIn &s : specs) {
+    k.push_back((uint64_t)(uintptr_t)s.x);
+    k.push_back(s.n);
+    k.push_back(s.zmax);
+  }
+  pulscan_opts o = a.opts;
+  o.stream = nullptr;
+  o.async = 0;
+  const uint64_t *ow = reinterpret_cast<const uint64_t *>(&o);
+  for (size_t i = 0; i < sizeof(o) / 8; ++i) k.push_back(ow[i]);
+  uint32_t sb;
+  memcpy(&sb, &a.sigma, 4);
+  k.push_back(((uint64_t)a.chunk << 32) | a.block);
+  k.push_back(((uint64_t)a.tile << 32) | sb);
+  k.push_back((uint64_t)(uintptr_t)a.out->data);
+  k.push_back(a.out->capacity);
+  k.push_back((uint64_t)a.out->on_device);
+  k.push_back((uint64_t)(uintptr_t)a.out->count_device);
+  return k;
+}
+
+void drop_graph(pulscan_ctx *ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  ctx->graph_exec = nullptr;
+  ctx->graph_key.clear();
+}
+
+// A search replayed from a captured graph: the first call with a given set
+// of arguments runs normally (growing buffers and filling the caches), then
+// its launches are captured on the context's own stream; later calls with
+// the same arguments launch the graph on the caller's stream.
+int run_graph(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a) {
+  hipStream_t stream = (hipStream_t)a.opts.stream;
+  std::vector<uint64_t> key = graph_key_of(specs, a);
+  Pending pd;
+  if (!(ctx->graph_exec && key == ctx->graph_key && ctx->epoch == ctx->graph_epoch)) {
+    drop_graph(ctx);
+    int st = enqueue_any(ctx, specs, a, &pd);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(stream));
+    RunArgs c = a;
+    c.opts.stream = ctx->cap_stream;
+    hipGraph_t graph = nullptr;
+    const uint64_t before = ctx->epoch;
+    HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue_any(ctx, specs, c, &pd);
+    const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (!st && ce == hipSuccess && ctx->epoch != before) st = PULSCAN_EHIP;  // cannot happen
+    if (st || ce != hipSuccess) {
+      (void)hipGetLastError();
+      if (graph) (void)hipGraphDestroy(graph);
+      return st ? st : PULSCAN_EHIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->graph_exec = nullptr;
+      return PULSCAN_EHIP;
+    }
+    ctx->graph_key = key;
+    ctx->graph_epoch = ctx->epoch;
+    // this call's results came from the direct run
+    return a.opts.async ? PULSCAN_OK : finish(ctx, a, pd);
+  }
+  HIP_TRY(hipGraphLaunch(ctx->graph_exec, stream));
+  if (a.opts.async) return PULSCAN_OK;
+  // the same launches as the captured run: its buffers and flags
+  pd.cnt = static_cast<Counters *>(ctx->counters.p);
+  pd.best = a.opts.best_per_chunk != 0 || a.opts.power_fp16 != 0;
+  pd.host = !a.out->on_device;
+  uint64_t worst = 0;
+  for (const SpecIn &s : specs)
+    for (uint32_t H = 1; H <= (uint32_t)(a.opts.numharm > 1 ? a.opts.numharm : 1); ++H)
+      worst += (s.n / H + a.chunk - 1) / a.chunk * (uint64_t)s.zmax;
+  pd.cap = a.out->capacity;
+  if (pd.host && pd.cap > worst) pd.cap = worst;
+  return finish(ctx, a, pd);
 }
 
 int run(pulscan_ctx *ctx, std::vector<SpecIn> specs, const RunArgs &a) {
   HIP_TRY(hipSetDevice(ctx->device));
   for (size_t s = 0; s < specs.size(); ++s) specs[s].spec_id = (uint32_t)s;
-  if (a.kind == kRunSearch && a.opts.numharm > 1) return run_harmonics(ctx, specs, a);
-  return run_core(ctx, specs, a);
+  if (a.kind == kRunSearch && a.opts.graph) return run_graph(ctx, specs, a);
+  Pending pd;
+  int st = enqueue_any(ctx, specs, a, &pd);
+  if (st) return st;
+  if (a.kind != kRunSearch) {
+    HIP_TRY(hipStreamSynchronize((hipStream_t)a.opts.stream));
+    return PULSCAN_OK;
+  }
+  return a.opts.async ? PULSCAN_OK : finish(ctx, a, pd);
+}
+
+// Autotuner of the batched call with chunk 0: every (chunk, tile) the
+// kernels accept, chunk from {256, 1024, 4096}, is timed on the batch itself
+// (the second of two runs, the first warms the caches), and the fastest is
+// kept for batches of the same signature.  The chunk changes what the search
+// reports and is returned to the caller; the tile only changes the speed.
+int autotune(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a,
+             uint32_t *chunk_out, uint32_t *tile_out) {
+  std::vector<uint64_t> sig;
+  uint64_t nsum = 0;
+  uint32_t zmax_max = 0;
+  for (const SpecIn &s : specs) {
+    nsum += s.n;
+    zmax_max = s.zmax > zmax_max ? s.zmax : zmax_max;
+  }
+  sig.push_back(specs.size());
+  sig.push_back(nsum >> 20);
+  sig.push_back(zmax_max);
+  sig.push_back((uint64_t)a.opts.norm_block);
+  sig.push_back((uint64_t)a.opts.numharm);
+  sig.push_back((uint64_t)a.opts.width_search);
+  sig.push_back((uint64_t)a.opts.dense);
+  sig.push_back((uint64_t)a.opts.power_fp16);
+  for (auto &e : ctx->tuned)
+    if (e.first == sig) {
+      *chunk_out = e.second.first;
+      *tile_out = e.second.second;
+      return PULSCAN_OK;
+    }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t stream = (hipStream_t)a.opts.stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best_ms = INFINITY;
+  uint32_t best_c = 0, best_t = 0;
+  int st = PULSCAN_OK;
+  static const uint32_t chunks[] = {256, 1024, 4096};
+  for (uint32_t C : chunks) {
+    const uint32_t B = a.opts.norm_block > 0 ? (uint32_t)a.opts.norm_block : C;
+    bool ok = true;
+    uint64_t worst = 0;
+    for (const SpecIn &s : specs) {
+      uint32_t b = 0;
+      if (check_spectrum(s.x, s.n, (int)s.zmax, (int)C, a.opts, &b) != PULSCAN_OK) ok = false;
+      for (uint32_t H = 1; H <= (uint32_t)(a.opts.numharm > 1 ? a.opts.numharm : 1); ++H)
+        worst += (s.n / H + C - 1) / C * (uint64_t)s.zmax;
+    }
+    if (!ok) continue;
+    st = grow(ctx, ctx->tune_out, (size_t)(worst + 1) * sizeof(pulscan_candidate), false);
+    if (st) break;
+    Counters *cnt = nullptr;
+    for (uint32_t T : tile_choices(C, B, zmax_max, a.opts.power_fp16 != 0)) {
+      RunArgs t = a;
+      t.chunk = C;
+      t.block = B;
+      t.tile = T;
+      pulscan_candidates o{};
+      o.data = static_cast<pulscan_candidate *>(ctx->tune_out.p);
+      o.capacity = worst + 1;
+      o.on_device = 1;
+      t.out = &o;
+      t.opts.async = 1;
+      t.opts.graph = 0;
+      float ms = INFINITY;
+      for (int rep = 0; rep < 2 && st == PULSCAN_OK; ++rep) {
+        HIP_TRY(hipEventRecord(e0, stream));
+        Pending pd;
+        st = enqueue_any(ctx, specs, t, &pd);
+        cnt = pd.cnt;
+        HIP_TRY(hipEventRecord(e1, stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (st == PULSCAN_EUNSUPPORTED) {
+        st = PULSCAN_OK;
+        continue;
+      }
+      if (st) break;
+      (void)cnt;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_c = C;
+        best_t = T;
+      }
+    }
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (best_c == 0) return PULSCAN_EUNSUPPORTED;
+  ctx->tuned.emplace_back(sig, std::make_pair(best_c, best_t));
+  *chunk_out = best_c;
+  *tile_out = best_t;
+  return PULSCAN_OK;
 }
 
 std::mutex g_default_mu;
@@ -545,7 +803,8 @@ int pulscan_ctx_create(pulscan_ctx **out, int device) {
   pulscan_ctx *ctx = new (std::nothrow) pulscan_ctx();
   if (!ctx) return PULSCAN_ENOMEM;
   ctx->device = device;
-  if (hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreate(&ctx->cap_stream) != hipSuccess) {
     (void)hipGetLastError();
     pulscan_ctx_destroy(ctx);
     return PULSCAN_EHIP;
@@ -558,9 +817,12 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  drop_graph(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   DevBuf *bufs[] = {&ctx->thr,    &ctx->pool,   &ctx->tile_word, &ctx->tile_prefix,
                     &ctx->counters, &ctx->outbuf, &ctx->descs,  &ctx->jobs,
-                    &ctx->allbuf, &ctx->hpow,   &ctx->hsum,     &ctx->hjobs};
+                    &ctx->allbuf, &ctx->hpow,   &ctx->hsum,     &ctx->hjobs,
+                    &ctx->tune_out, &ctx->stats};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -621,24 +883,39 @@ int pulscan_search_batched(pulscan_ctx *ctx, int nspec, const pulscan_complex *c
     return PULSCAN_EINVAL;
   int st = check_out(out, o.async != 0);
   if (st) return st;
-  const int c = chunk > 0 ? chunk : 1024;
-  uint32_t block = 0;
   std::vector<SpecIn> specs(nspec);
   for (int s = 0; s < nspec; ++s) {
-    uint32_t b = 0;
-    st = check_spectrum(spectra[s], nbins[s], zmax[s], c, o, &b);
-    if (st) return st;
-    block = b;
+    if (!spectra[s] || zmax[s] < 1 || nbins[s] == 0) return PULSCAN_EINVAL;
     specs[s] = SpecIn{spectra[s], nbins[s], (uint32_t)zmax[s]};
   }
-  if (chunk_used) *chunk_used = c;
   RunArgs a;
   a.kind = kRunSearch;
-  a.chunk = (uint32_t)c;
-  a.block = block;
   a.sigma = sigma_thresh;
   a.opts = o;
   a.out = out;
+  uint32_t c = (uint32_t)chunk, tile = 0;
+  if (chunk == 0) {
+    // validate at the default chunk first, so that argument errors are not
+    // masked by the tuner's search over chunks
+    for (int s = 0; s < nspec; ++s) {
+      uint32_t b = 0;
+      st = check_spectrum(spectra[s], nbins[s], zmax[s], 1024, o, &b);
+      if (st == PULSCAN_EINVAL) return st;
+    }
+    st = autotune(ctx, specs, a, &c, &tile);
+    if (st) return st;
+  }
+  uint32_t block = 0;
+  for (int s = 0; s < nspec; ++s) {
+    uint32_t b = 0;
+    st = check_spectrum(spectra[s], nbins[s], zmax[s], (int)c, o, &b);
+    if (st) return st;
+    block = b;
+  }
+  if (chunk_used) *chunk_used = (int)c;
+  a.chunk = c;
+  a.block = block;
+  a.tile = tile;
   return run(ctx, specs, a);
 }
 

@@ -141,6 +141,13 @@ __device__ __forceinline__ float wave_mom1(const float (&a)[EPL], float c) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))) * scale;
 }
 
+// A power as stored in the LDS tile: FP32, or FP16 (round to nearest;
+// values beyond the FP16 range become +inf, which the re-check catches).
+template <typename PT>
+__device__ __forceinline__ PT to_pt(float v) {
+  return (PT)v;
+}
+
 // Order-preserving map of a float to a 32-bit unsigned integer and back.
 __device__ __forceinline__ uint32_t ord_f32(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -215,9 +222,9 @@ __device__ __forceinline__ void load_block(const float2 *__restrict__ x, uint32_
 // Normalise a loaded block and write its power into the tile's LDS array for
 // every bin of the block that the tile needs (tile-relative index below
 // `need`).  Executed by one whole wave.
-template <int K, int EPL>
+template <int K, int EPL, typename PT>
 __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, uint32_t t0,
-                                                uint32_t need, uint32_t T, float *Pl,
+                                                uint32_t need, uint32_t T, PT *Pl,
                                                 uint32_t lane, float *P_out, float *stats_out) {
   constexpr uint32_t B = 64 * EPL;
   constexpr int PITCH = pitch_of<K>();
@@ -257,7 +264,7 @@ __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, 
     for (int m = 0; m < EPL; ++m) {
       const float a = fmaf(re[m], inv_re, off_re);
       const float c = fmaf(im[m], inv_im, off_im);
-      Pl[base + (m / K) * (K * PITCH) + (64 / K) * (m % K)] = fmaf(a, a, c * c);
+      Pl[base + (m / K) * (K * PITCH) + (64 / K) * (m % K)] = to_pt<PT>(fmaf(a, a, c * c));
     }
   } else {
 #pragma unroll
@@ -267,7 +274,7 @@ __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, 
         const float a = fmaf(re[m], inv_re, off_re);
         const float c = fmaf(im[m], inv_im, off_im);
         const float P = fmaf(a, a, c * c);
-        Pl[paddr<K>(t - t0)] = P;
+        Pl[paddr<K>(t - t0)] = to_pt<PT>(P);
         if (P_out && t - t0 < T) P_out[t] = P;
       }
     }
@@ -327,18 +334,18 @@ constexpr int ks_of() {
 // Load the KS + K - 1 powers P[b0 + k0 + wb + j] (j < KS + K - 1) that the
 // starts k0 .. k0+KS-1 of lane L (b0 = L*K) read in width block wb+1 ..
 // wb+K.  They lie in lane columns L + wb/K and L + wb/K + 1.
-template <int K>
-__device__ __forceinline__ void load_window(const float *__restrict__ Pl, uint32_t L, uint32_t wb,
+template <int K, typename PT>
+__device__ __forceinline__ void load_window(const PT *__restrict__ Pl, uint32_t L, uint32_t wb,
                                             int k0, float (&q)[ks_of<K>() + K - 1]) {
   constexpr int PITCH = pitch_of<K>();
   constexpr int KS = ks_of<K>();
   const uint32_t La = L + wb / K, Lb = La + 1;
-  const float *pa = Pl + (La >> 6) * (K * PITCH) + (La & 63);
-  const float *pb = Pl + (Lb >> 6) * (K * PITCH) + (Lb & 63);
+  const PT *pa = Pl + (La >> 6) * (K * PITCH) + (La & 63);
+  const PT *pb = Pl + (Lb >> 6) * (K * PITCH) + (Lb & 63);
 #pragma unroll
   for (int j = 0; j < KS + K - 1; ++j) {
     const int r = k0 + j;  // k0 is a multiple of KS, known at compile time after unrolling
-    q[j] = r < K ? pa[r * PITCH] : pb[(r - K) * PITCH];
+    q[j] = r < K ? (float)pa[r * PITCH] : (float)pb[(r - K) * PITCH];
   }
 }
 
@@ -386,8 +393,8 @@ __device__ __forceinline__ void width_block(const float (&q)[ks_of<K>() + K - 1]
 // tile), lane l owning starts g*64K + l*K .. +K-1: every width 1..zc in the
 // canonical order, with the per-lane maximum, the threshold test and the
 // merge into the chunk's slot for every width.
-template <int K>
-__device__ __forceinline__ void bank_dense(const float *__restrict__ Pl, uint32_t g, uint32_t lane,
+template <int K, typename PT>
+__device__ __forceinline__ void bank_dense(const PT *__restrict__ Pl, uint32_t g, uint32_t lane,
                                            const_fptr thr, uint32_t zmax, uint32_t zc,
                                            unsigned long long *slot_row, uint32_t bin0) {
   constexpr int KS = ks_of<K>();
@@ -398,7 +405,7 @@ __device__ __forceinline__ void bank_dense(const float *__restrict__ Pl, uint32_
 #pragma unroll
     for (int k = 0; k < KS; ++k) hb[k] = t[k] = 0.f;
     for (uint32_t wb = 0; wb < zc; wb += K) {
-      load_window<K>(Pl, L, wb, k0, q);
+      load_window<K, PT>(Pl, L, wb, k0, q);
       float Tv[K];  // this block's thresholds (scalar loads)
 #pragma unroll
       for (int u = 0; u < K; ++u) Tv[u] = thr[wb + u];
@@ -422,27 +429,27 @@ constexpr int kSub = 4;  // widths per bound check inside the first width block
 // 1..K, the lowest thresholds) is checked every kSub widths from the powers
 // themselves; later blocks add one K-bin group sum per block.
 // CLAMP: the tile holds -inf past the end of the spectrum; count those as 0.
-template <int K, bool CLAMP>
-__device__ __forceinline__ uint32_t bound_lane(const float *__restrict__ Pl,
+template <int K, bool CLAMP, typename PT>
+__device__ __forceinline__ uint32_t bound_lane(const PT *__restrict__ Pl,
                                                const float *__restrict__ Sg, uint32_t g,
                                                uint32_t lane, const float *__restrict__ Tb1,
                                                const float *__restrict__ Tb, uint32_t nblk) {
   constexpr int PITCH = pitch_of<K>();
   constexpr int S = K < kSub ? K : kSub;
   // the lane's first 2K - 1 bins, summed as they are read
-  const float *bp = Pl + g * (K * PITCH) + lane;
+  const PT *bp = Pl + g * (K * PITCH) + lane;
   const uint32_t L1 = lane + 1;
-  const float *bq = Pl + (g + (L1 >> 6)) * (K * PITCH) + (L1 & 63);
+  const PT *bq = Pl + (g + (L1 >> 6)) * (K * PITCH) + (L1 & 63);
   float U = 0.f;
 #pragma unroll
   for (int j = 0; j < K - 1; ++j) {
-    const float v = bp[j * PITCH];
+    const float v = (float)bp[j * PITCH];
     U += CLAMP ? fmaxf(v, 0.f) : v;
   }
   bool hit = false;
 #pragma unroll
   for (int u = 0; u < K; ++u) {
-    const float v = u == 0 ? bp[(K - 1) * PITCH] : bq[(u - 1) * PITCH];
+    const float v = u == 0 ? (float)bp[(K - 1) * PITCH] : (float)bq[(u - 1) * PITCH];
     U += CLAMP ? fmaxf(v, 0.f) : v;
     if ((u + 1) % S == 0) hit = hit || (U >= Tb1[u / S]);
   }
@@ -465,8 +472,8 @@ __device__ __forceinline__ uint32_t bound_lane(const float *__restrict__ Pl,
 // bins LK+s .. LK+K-1, and t holds the first s bins of group L+b.  A window
 // that already reaches past the spectrum's end (tile bin `rem`) is -inf, as
 // the dense route's running sum would be.
-template <int K>
-__device__ __forceinline__ void eval_unit(const float *__restrict__ Pl,
+template <int K, typename PT>
+__device__ __forceinline__ void eval_unit(const PT *__restrict__ Pl,
                                           const float *__restrict__ Sg,
                                           const float *__restrict__ Tl, uint32_t L, uint32_t b,
                                           int k0, uint32_t rem, uint32_t zmax,
@@ -478,13 +485,13 @@ __device__ __forceinline__ void eval_unit(const float *__restrict__ Pl,
 #pragma unroll
     for (int k = 0; k < KS; ++k) hb[k] = t[k] = 0.f;
   } else {
-    const float *po = Pl + (L >> 6) * (K * PITCH) + (L & 63);
+    const PT *po = Pl + (L >> 6) * (K * PITCH) + (L & 63);
 #pragma unroll
     for (int k = KS - 1; k >= 0; --k) {
       // H_s adds bins s .. K-1 in increasing order from zero
-      float a = po[(k0 + k) * PITCH];
+      float a = (float)po[(k0 + k) * PITCH];
 #pragma unroll
-      for (int v = k0 + k + 1; v < K; ++v) a += po[v * PITCH];
+      for (int v = k0 + k + 1; v < K; ++v) a += (float)po[v * PITCH];
       hb[k] = a;
     }
     for (uint32_t j = 1; j < b; ++j) {
@@ -494,53 +501,69 @@ __device__ __forceinline__ void eval_unit(const float *__restrict__ Pl,
     }
     // t: the first s bins of group L+b, s = k0 + k
     const uint32_t Lg = L + b;
-    const float *pg = Pl + (Lg >> 6) * (K * PITCH) + (Lg & 63);
+    const PT *pg = Pl + (Lg >> 6) * (K * PITCH) + (Lg & 63);
     float pre = 0.f;
 #pragma unroll
-    for (int v = 0; v < k0; ++v) pre += pg[v * PITCH];
+    for (int v = 0; v < k0; ++v) pre += (float)pg[v * PITCH];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       t[k] = pre;
-      if (k + 1 < KS) pre += pg[(k0 + k) * PITCH];
+      if (k + 1 < KS) pre += (float)pg[(k0 + k) * PITCH];
     }
 #pragma unroll
     for (int k = 0; k < KS; ++k)
       if (L * K + k0 + k + b * K > rem) hb[k] = -INFINITY;
   }
-  load_window<K>(Pl, L, b * K, k0, q);
+  load_window<K, PT>(Pl, L, b * K, k0, q);
   width_block<K>(q, hb, t, k0, Tl + b * K, b * K, zmax, slot_row, bin0);
 }
 
 // Exclusive scan of the per-tile candidate counts by the workgroup that
-// finished last.  Each tile publishes its count as one relaxed 64-bit word
+// started last.  Each tile publishes its count as one relaxed 64-bit word
 // (generation << 32 | count); a word of an earlier launch is waited for
-// rather than fenced, so no tile pays for a device-wide release.  Thread t
+// rather than fenced, so no tile pays for a device-wide release.  The
+// generation lives in device memory: every tile reads it when it starts and
+// the scanning tile advances it after every tile has published, so launches
+// replayed from a graph still tag their words apart.  Thread t
 // sums a contiguous run of tiles, the run totals are scanned across the
 // workgroup, and each thread writes its run's prefixes.  Also records the
 // total and the staging overflow, and re-arms the pool head and the
 // finished-tile counter for the next launch.
 constexpr uint32_t kWordSpin = 1u << 22;  // polls per word before giving up
 
-__device__ __forceinline__ uint32_t tile_count_of(const BankParams &p, uint64_t i, bool &lost) {
+__device__ __forceinline__ uint32_t tile_count_of(const BankParams &p, uint64_t i, uint32_t gen,
+                                                  bool &lost) {
   unsigned long long v = 0;
   for (uint32_t k = 0; k < kWordSpin; ++k) {
     v = __hip_atomic_load(p.tile_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((uint32_t)(v >> 32) == p.gen) return (uint32_t)v;
+    if ((uint32_t)(v >> 32) == gen) return (uint32_t)v;
     __builtin_amdgcn_s_sleep(1);
   }
   lost = true;  // reported through the overflow flag
   return 0u;
 }
 
-__device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uint32_t *wave_sum,
-                           uint32_t *lost_any) {
+__device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uint32_t gen,
+                           uint32_t *wave_sum, uint32_t *lost_any) {
   const uint32_t lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
   const uint64_t T = p.total_tiles;
   const uint64_t per = (T + nthr - 1) / nthr;
   const uint64_t lo = min((uint64_t)tid * per, T), hi = min(lo + per, T);
   bool lost = false;
   uint32_t mine = 0;
-  for (uint64_t i = lo; i < hi; ++i) mine += tile_count_of(p, i, lost);
+  // eight independent loads in flight; a word not yet tagged with this
+  // launch's generation is then waited for on its own
+  uint64_t i = lo;
+  for (; i + 8 <= hi; i += 8) {
+    unsigned long long v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      v[k] = __hip_atomic_load(p.tile_word + i + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      mine += (uint32_t)(v[k] >> 32) == gen ? (uint32_t)v[k] : tile_count_of(p, i + k, gen, lost);
+  }
+  for (; i < hi; ++i) mine += tile_count_of(p, i, gen, lost);
   if (lost) atomicOr(lost_any, 1u);
   uint32_t incl = mine;
 #pragma unroll
@@ -556,9 +579,9 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
     tot += wave_sum[v];
   }
   run += incl - mine;
-  for (uint64_t i = lo; i < hi; ++i) {
-    p.tile_prefix[i] = run;
-    run += (uint32_t)__hip_atomic_load(p.tile_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint64_t j = lo; j < hi; ++j) {
+    p.tile_prefix[j] = run;
+    run += (uint32_t)__hip_atomic_load(p.tile_word + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (tid == 0) {
@@ -568,6 +591,7 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
     *p.overflow = *lost_any ? 2u : (tot > p.pool_cap ? 1u : 0u);
     __hip_atomic_store(p.pool_head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(p.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p.gen, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -582,7 +606,7 @@ constexpr int waves_per_eu_for() {
   return EPL >= 64 ? 1 : 6;
 }
 
-template <int K, int EPL>
+template <int K, int EPL, typename PT>
 __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void bank_kernel(
     BankParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -592,6 +616,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
   __shared__ uint32_t n_items;
   __shared__ uint32_t is_last;
   __shared__ uint32_t lost_any;
+  __shared__ uint32_t launch_gen;
   constexpr uint32_t SEG = 64 * K;
   constexpr uint32_t B = 64 * EPL;
   constexpr int PITCH = pitch_of<K>();
@@ -608,7 +633,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
   float *Tb = Tb1 + 4;
   float *Sg = Tb + p.zc_max_pad / K + 4;
   uint32_t *items = reinterpret_cast<uint32_t *>(Sg + p.nseg_lds * 64);  // T / K entries
-  float *Pl = reinterpret_cast<float *>(items + T / K);
+  PT *Pl = reinterpret_cast<PT *>(items + T / K);
 
   // One tile per workgroup.  Workgroups are dealt round-robin to the 8
   // XCDs; give each XCD a contiguous run of tiles so the halo a tile shares
@@ -620,6 +645,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
   {
     const uint64_t tg = first_tile;
     uint32_t ticket = 0;  // thread 0: this tile's place in the order tiles start
+    uint32_t gen = 0;     // thread 0: this launch's generation tag
     int sidx = 0;
     if (p.nspec > 1) {
       int lo = 0, hi = p.nspec - 1;
@@ -656,7 +682,11 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       // the tile that starts last scans the per-tile counts once every tile
       // has published its count; taking the ticket now hides its latency
       // behind the spectrum loads
-      if (p.mode == kModeSearch) ticket = atomicAdd(p.done, 1u);
+      if (p.mode == kModeSearch) {
+        ticket = atomicAdd(p.done, 1u);
+        gen = __hip_atomic_load(p.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (gen == 0u) gen = 1u;  // words start at generation 0
+      }
     }
     if (!power_only) {
     for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
@@ -678,17 +708,19 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
     // halo bins beyond what any width <= zmax reads are 0 (read only by the
     // unrecorded widths zmax+1..zc and by the pruning bound)
     for (uint32_t i = need + tid; i < span; i += nthr)
-      Pl[paddr<K>(i)] = i < rem ? 0.f : -INFINITY;
+      Pl[paddr<K>(i)] = to_pt<PT>(i < rem ? 0.f : -INFINITY);
     if (p.from_power) {
       const float *pw = reinterpret_cast<const float *>(d.x);
-      for (uint32_t i = tid; i < need; i += nthr) Pl[paddr<K>(i)] = pw[t0 + i];
+      for (uint32_t i = tid; i < need; i += nthr) Pl[paddr<K>(i)] = to_pt<PT>(pw[t0 + i]);
     } else if (have) {
       const bool dbg = p.mode == kModeTables;
       float *po = power_only ? d.aux : dbg ? p.P_out : nullptr;
-      float *so = dbg ? p.stats_out : nullptr;
+      // the half-precision search keeps every block's statistics for its
+      // FP32 re-check of candidates near the threshold
+      float *so = dbg ? p.stats_out : (p.mode == kModeSearch && sizeof(PT) == 2) ? d.aux : nullptr;
       for (uint32_t b = bfirst + wave; b <= blast; b += nw) {
         if (b != bfirst + wave) load_block<EPL>(d.x, n, b, lane, bd);
-        normalise_block<K, EPL>(bd, b, t0, need, T, Pl, lane, po, so);
+        normalise_block<K, EPL, PT>(bd, b, t0, need, T, Pl, lane, po, so);
       }
     }
     }
@@ -703,14 +735,14 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       // K-bin group sums of the whole span (inputs of the pruning bound)
       const uint32_t ngroups = span / K;
       for (uint32_t j = tid; j < ngroups; j += nthr) {
-        const float *cp = Pl + (j >> 6) * (K * PITCH) + (j & 63);
+        const PT *cp = Pl + (j >> 6) * (K * PITCH) + (j & 63);
         float a = 0.f;
         if (clamp) {
 #pragma unroll
-          for (int v = 0; v < K; ++v) a += fmaxf(cp[v * PITCH], 0.f);
+          for (int v = 0; v < K; ++v) a += fmaxf((float)cp[v * PITCH], 0.f);
         } else {
 #pragma unroll
-          for (int v = 0; v < K; ++v) a += cp[v * PITCH];
+          for (int v = 0; v < K; ++v) a += (float)cp[v * PITCH];
         }
         Sg[j] = a;
       }
@@ -725,8 +757,8 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       // flagged lanes become work items of a cooperative exact pass
       for (uint32_t g = wave; g < nseg_tile; g += nw) {
         if (g * SEG >= rem) break;
-        const uint32_t fl = clamp ? bound_lane<K, true>(Pl, Sg, g, lane, Tb1, Tb, nblk)
-                                  : bound_lane<K, false>(Pl, Sg, g, lane, Tb1, Tb, nblk);
+        const uint32_t fl = clamp ? bound_lane<K, true, PT>(Pl, Sg, g, lane, Tb1, Tb, nblk)
+                                  : bound_lane<K, false, PT>(Pl, Sg, g, lane, Tb1, Tb, nblk);
         const unsigned long long mask = __ballot(fl < nblk);
         if (mask) {
           uint32_t base = 0;
@@ -755,9 +787,9 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
           const uint32_t L = it >> 12;
           unsigned long long *row = slots + (size_t)((L * K) / C) * zmax;
           if (NH == 1 || j % NH == 0)
-            eval_unit<K>(Pl, Sg, Tl, L, b, 0, rem, zmax, row, t0 + L * K);
+            eval_unit<K, PT>(Pl, Sg, Tl, L, b, 0, rem, zmax, row, t0 + L * K);
           else
-            eval_unit<K>(Pl, Sg, Tl, L, b, ks_of<K>(), rem, zmax, row, t0 + L * K);
+            eval_unit<K, PT>(Pl, Sg, Tl, L, b, ks_of<K>(), rem, zmax, row, t0 + L * K);
         }
       }
     } else {
@@ -766,7 +798,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
         const uint32_t seg0 = g * SEG;
         if (seg0 >= rem) break;
         any_dense = 1u;
-        bank_dense<K>(Pl, g, lane, thr, zmax, zc, slots + (size_t)(seg0 / C) * zmax,
+        bank_dense<K, PT>(Pl, g, lane, thr, zmax, zc, slots + (size_t)(seg0 / C) * zmax,
                       t0 + seg0 + lane * K);
       }
     }
@@ -804,9 +836,10 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
         // the pool reservation has been performed before the count is
         // published, so the scanning tile may re-arm the pool head
         __builtin_amdgcn_s_waitcnt(0);
-        __hip_atomic_store(p.tile_word + tg, ((unsigned long long)p.gen << 32) | tot,
+        __hip_atomic_store(p.tile_word + tg, ((unsigned long long)gen << 32) | tot,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         is_last = ticket == (uint32_t)(p.total_tiles - 1) ? 1u : 0u;
+        launch_gen = gen;
         lost_any = 0u;
       }
       __syncthreads();
@@ -827,7 +860,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
         ++rank;
       }
       // the last tile to finish scans the per-tile counts
-      if (is_last) scan_tiles(p, tid, nthr, wave_sum, &lost_any);
+      if (is_last) scan_tiles(p, tid, nthr, launch_gen, wave_sum, &lost_any);
     } else {
       for (uint32_t i = tid; i < nsl; i += nthr) {
         const unsigned long long key = slots[i];
@@ -843,7 +876,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
 
 template <int K>
 static size_t lds_need_k(uint32_t T, uint32_t C, uint32_t zmax_max, uint32_t *nseg,
-                         uint32_t *zc_pad) {
+                         uint32_t *zc_pad, uint32_t pbytes) {
   const uint32_t zc = round_widths(zmax_max, K);
   const uint32_t segb = 64u * (uint32_t)K;
   *nseg = (T + zc + segb - 1) / segb;
@@ -853,17 +886,17 @@ static size_t lds_need_k(uint32_t T, uint32_t C, uint32_t zmax_max, uint32_t *ns
          + (4 + (size_t)(*zc_pad) / K + 4) * 4u       // bound thresholds
          + (size_t)(*nseg) * 64u * 4u                 // group sums
          + (size_t)(T / K) * 4u                       // cooperative work items
-         + (size_t)(*nseg) * K * pitch_of<K>() * 4u;  // power tile
+         + (size_t)(*nseg) * K * pitch_of<K>() * pbytes;  // power tile
 }
 
 static size_t lds_need(int K, uint32_t T, uint32_t C, uint32_t zmax_max, uint32_t *nseg,
-                       uint32_t *zc_pad) {
+                       uint32_t *zc_pad, uint32_t pbytes) {
   switch (K) {
-    case 1: return lds_need_k<1>(T, C, zmax_max, nseg, zc_pad);
-    case 2: return lds_need_k<2>(T, C, zmax_max, nseg, zc_pad);
-    case 4: return lds_need_k<4>(T, C, zmax_max, nseg, zc_pad);
-    case 8: return lds_need_k<8>(T, C, zmax_max, nseg, zc_pad);
-    default: return lds_need_k<16>(T, C, zmax_max, nseg, zc_pad);
+    case 1: return lds_need_k<1>(T, C, zmax_max, nseg, zc_pad, pbytes);
+    case 2: return lds_need_k<2>(T, C, zmax_max, nseg, zc_pad, pbytes);
+    case 4: return lds_need_k<4>(T, C, zmax_max, nseg, zc_pad, pbytes);
+    case 8: return lds_need_k<8>(T, C, zmax_max, nseg, zc_pad, pbytes);
+    default: return lds_need_k<16>(T, C, zmax_max, nseg, zc_pad, pbytes);
   }
 }
 
@@ -881,7 +914,9 @@ constexpr size_t kLdsBudget = 64 * 1024;     // per workgroup
 constexpr size_t kLdsPreferred = 53 * 1024;  // three workgroups share a CU's 160 KiB
 constexpr uint32_t kMaxWaves = 8;
 
-bool choose_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, uint64_t n_hint, Geometry *g) {
+bool choose_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, uint64_t n_hint, Geometry *g,
+                     uint32_t tile, bool fp16) {
+  const uint32_t pb = fp16 ? 2u : 4u;
   if (C == 0 || C % 64 != 0 || C > (uint32_t)kMaxTile) return false;
   if (B != 64 && B != 256 && B != 1024 && B != 4096) return false;
   if (zmax_max == 0 || zmax_max > 4096) return false;
@@ -897,9 +932,17 @@ bool choose_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, uint64_t n_hint,
   // smallest tile may use up to the per-workgroup budget) and enough tiles
   // to fill the GPU
   uint64_t T = 0;
-  for (uint64_t t = L0; t <= (uint64_t)kMaxTile; t += L0) {
+  if (tile) {
+    // a tile asked for (by the autotuner): it must be a multiple of L0 that
+    // fits the wave and LDS limits
+    if (tile % L0 != 0 || tile > (uint64_t)kMaxTile) return false;
+    if (tile / B + halo > wmax && tile > L0) return false;
+    if (lds_need(K, tile, C, zmax_max, &nseg, &zcp, pb) > kLdsBudget) return false;
+    T = tile;
+  }
+  for (uint64_t t = L0; !tile && t <= (uint64_t)kMaxTile; t += L0) {
     if (t / B + halo > wmax && t > L0) break;
-    const size_t lds = lds_need(K, (uint32_t)t, C, zmax_max, &nseg, &zcp);
+    const size_t lds = lds_need(K, (uint32_t)t, C, zmax_max, &nseg, &zcp, pb);
     if (lds > kLdsBudget || (lds > kLdsPreferred && t > L0)) break;
     if (t > L0 && n_hint / t < 256) break;
     T = t;
@@ -910,43 +953,62 @@ bool choose_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, uint64_t n_hint,
   uint32_t nw = (uint32_t)(T / B) + halo;
   g->waves = (int)(nw < 1 ? 1 : (nw > wmax ? wmax : nw));
   g->tile = (uint32_t)T;
-  g->lds_bytes = lds_need(K, g->tile, C, zmax_max, &nseg, &zcp);
+  g->lds_bytes = lds_need(K, g->tile, C, zmax_max, &nseg, &zcp, pb);
+  g->fp16 = fp16;
   g->nseg_lds = nseg;
   g->zc_max_pad = zcp;
   return true;
 }
 
-template <int K>
+// Tiles the kernels can run for chunk C, block B and zmax_max: the multiples
+// of the smallest legal tile that fit the wave and LDS limits.
+std::vector<uint32_t> tile_choices(uint32_t C, uint32_t B, uint32_t zmax_max, bool fp16) {
+  std::vector<uint32_t> out;
+  Geometry g;
+  if (!choose_geometry(C, B, zmax_max, ~0ull, &g, 0, fp16)) return out;
+  const uint64_t L0 = lcm_u(lcm_u(C, B), 64ull * g.K);
+  for (uint64_t t = L0; t <= (uint64_t)kMaxTile; t += L0) {
+    Geometry h;
+    if (!choose_geometry(C, B, zmax_max, ~0ull, &h, (uint32_t)t, fp16)) break;
+    out.push_back((uint32_t)t);
+  }
+  return out;
+}
+
+template <int K, typename PT>
 static hipError_t launch_k(int EPL, uint64_t grid, uint32_t threads, size_t lds,
                            const BankParams &p, hipStream_t stream) {
+  const dim3 gd((uint32_t)grid), bd(threads);
   switch (EPL) {
-    case 1:
-      hipLaunchKernelGGL((bank_kernel<K, 1>), dim3((uint32_t)grid), dim3(threads), lds, stream, p);
-      break;
-    case 4:
-      hipLaunchKernelGGL((bank_kernel<K, 4>), dim3((uint32_t)grid), dim3(threads), lds, stream, p);
-      break;
-    case 16:
-      hipLaunchKernelGGL((bank_kernel<K, 16>), dim3((uint32_t)grid), dim3(threads), lds, stream, p);
-      break;
+    case 1: hipLaunchKernelGGL((bank_kernel<K, 1, PT>), gd, bd, lds, stream, p); break;
+    case 4: hipLaunchKernelGGL((bank_kernel<K, 4, PT>), gd, bd, lds, stream, p); break;
+    case 16: hipLaunchKernelGGL((bank_kernel<K, 16, PT>), gd, bd, lds, stream, p); break;
     case 64:
-      hipLaunchKernelGGL((bank_kernel<K, 64>), dim3((uint32_t)grid), dim3(threads), lds, stream, p);
+      // 4096-bin blocks keep FP32 power only
+      if (sizeof(PT) != 4) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((bank_kernel<K, 64, float>), gd, bd, lds, stream, p);
       break;
-    default:
-      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_pt(const Geometry &g, const BankParams &p, uint64_t grid,
+                            uint32_t threads, hipStream_t stream) {
+  return g.fp16 ? launch_k<K, _Float16>(g.EPL, grid, threads, g.lds_bytes, p, stream)
+                : launch_k<K, float>(g.EPL, grid, threads, g.lds_bytes, p, stream);
 }
 
 hipError_t launch_bank(const Geometry &g, const BankParams &p, uint64_t grid, hipStream_t stream) {
   if (grid == 0) return hipSuccess;
   const uint32_t threads = 64u * (uint32_t)g.waves;
   switch (g.K) {
-    case 1: return launch_k<1>(g.EPL, grid, threads, g.lds_bytes, p, stream);
-    case 2: return launch_k<2>(g.EPL, grid, threads, g.lds_bytes, p, stream);
-    case 4: return launch_k<4>(g.EPL, grid, threads, g.lds_bytes, p, stream);
-    case 8: return launch_k<8>(g.EPL, grid, threads, g.lds_bytes, p, stream);
-    case 16: return launch_k<16>(g.EPL, grid, threads, g.lds_bytes, p, stream);
+    case 1: return launch_pt<1>(g, p, grid, threads, stream);
+    case 2: return launch_pt<2>(g, p, grid, threads, stream);
+    case 4: return launch_pt<4>(g, p, grid, threads, stream);
+    case 8: return launch_pt<8>(g, p, grid, threads, stream);
+    case 16: return launch_pt<16>(g, p, grid, threads, stream);
     default: return hipErrorInvalidValue;
   }
 }

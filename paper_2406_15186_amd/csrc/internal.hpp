@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "pulscan.h"
 
 namespace pulscan {
@@ -22,7 +24,8 @@ constexpr uint32_t kPoolMax = 1u << 26;  // staging-pool entries per context (1 
 struct SpecDesc {
   const float2 *x;        // complex spectrum (or, from-power mode, float power)
   const float *thr;       // per-width thresholds, zc entries (+inf beyond zmax)
-  float *aux;             // power mode: where the normalised power goes
+  float *aux;             // power mode: where the normalised power goes; FP16
+                          // search: the blocks' statistics (4 floats each)
   uint64_t tile_begin;    // first global tile of this series
   double ntrials;         // Bonferroni factor
   uint32_t n;             // bins
@@ -74,7 +77,7 @@ struct BankParams {
   uint32_t *pool_head;     // next free pool entry (re-armed to 0 by the scan)
   uint32_t *done;          // tiles finished (re-armed to 0 by the scan)
   unsigned long long *tile_word;  // per tile: gen << 32 | candidates it staged
-  uint32_t gen;            // this launch's generation (never 0; words start at 0)
+  uint32_t *gen;           // generation of the last launch (device; words start at 0)
   uint32_t *tile_prefix;   // per tile: exclusive prefix of the counts; [total_tiles] = total
   unsigned long long *total;   // candidate count (device)
   unsigned long long *total2;  // optional second destination (the caller's)
@@ -94,13 +97,18 @@ struct Geometry {
   uint32_t nseg_lds;
   uint32_t zc_max_pad;
   size_t lds_bytes;
+  bool fp16;      // power tile stored in FP16
 };
 
 // Geometry for chunk C, block B, the largest zmax of the launch and the
 // shortest spectrum (n_hint, to keep enough tiles); returns false when the
-// kernels cannot run it (too large for LDS, bad sizes, zmax > 4096).
+// kernels cannot run it (too large for LDS, bad sizes, zmax > 4096).  A
+// non-zero `tile` asks for that tile instead of the heuristic choice.
 bool choose_geometry(uint32_t chunk, uint32_t block, uint32_t zmax_max, uint64_t n_hint,
-                     Geometry *g);
+                     Geometry *g, uint32_t tile = 0, bool fp16 = false);
+// Every tile choose_geometry accepts for these sizes, smallest first.
+std::vector<uint32_t> tile_choices(uint32_t chunk, uint32_t block, uint32_t zmax_max,
+                                   bool fp16 = false);
 
 // Round zmax up to the width block of the bank kernel for K bins per lane.
 inline uint32_t round_widths(uint32_t zmax, int K) { return (zmax + K - 1) / K * K; }
@@ -136,18 +144,30 @@ struct EmitParams {
   uint32_t rblock;                 // > 0: report bin / rblock
   pulscan_candidate *out;
   uint64_t capacity;
+  int fp16;                        // FP16-stored search: re-check near the threshold
+  int from_power;                  // the series are power (re-check reads them)
+  uint32_t block;                  // normalisation block (re-check statistics)
+  float sigma;                     // the requested threshold
 };
 hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t grid,
                        hipStream_t stream);
 
-// Best candidate per (spectrum, stage, chunk) of the canonical list `all`
-// (count *total, at most all_cap stored): out[k] is the highest-sigma
-// candidate of the k-th run of equal keys (the first on ties); the number of
-// runs goes to *count and, if non-null, *count2.  One workgroup.
-hipError_t launch_best(const pulscan_candidate *all, const unsigned long long *total,
-                       uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
-                       unsigned long long *count, unsigned long long *count2,
-                       hipStream_t stream);
+// Final pass over the canonical list `all` (count *total, at most all_cap
+// stored): entries with NaN sigma (rejected by the FP32 re-check) are
+// dropped; with `best`, out[k] is the highest-sigma survivor of the k-th run
+// of equal (spectrum, stage, chunk) (the first on ties).  The number written
+// goes to *count and, if non-null, *count2.  One workgroup.
+hipError_t launch_finalize(const pulscan_candidate *all, const unsigned long long *total,
+                           uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
+                           unsigned long long *count, unsigned long long *count2, int best,
+                           hipStream_t stream);
+
+// FP16 power storage: the bank compares against thresholds kRecheckBand sigma
+// below the requested one, and every candidate below sigma + kRecheckBand
+// (or whose FP16 sum reached kRecheckPower, where FP16 inputs may have
+// saturated) is re-decided on its FP32 power.
+constexpr float kRecheckBand = 0.5f;
+constexpr float kRecheckPower = 60000.0f;
 
 // Harmonic stages 2..numharm of one power series (section 2.3): S_H has
 // floor(n / H) bins and starts at S + sum_{h=2}^{H-1} floor(n / h).

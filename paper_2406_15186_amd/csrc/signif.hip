@@ -130,6 +130,31 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
   return hipGetLastError();
 }
 
+// The FP32 boxcar power of the window [bin, bin + w) of a series: its powers
+// recomputed from the raw spectrum with its blocks' statistics exactly as the
+// bank kernel normalises them (or read, for a power series), summed in
+// increasing order.  The re-check of the FP16-stored search.
+__device__ float power32_window(const SpecDesc &d, uint32_t B, int from_power, uint32_t bin,
+                                uint32_t w) {
+  float acc = 0.f;
+  if (from_power) {
+    const float *P = reinterpret_cast<const float *>(d.x);
+    for (uint32_t j = bin; j < bin + w; ++j) acc += P[j];
+    return acc;
+  }
+  for (uint32_t j = bin; j < bin + w; ++j) {
+    const float *st = d.aux + 4 * (size_t)(j / B);
+    const float med_re = st[0], mad_re = st[1], med_im = st[2], mad_im = st[3];
+    const float inv_re = mad_re > 0.f ? 1.0f / (mad_re * kMadScale) : 0.f;
+    const float inv_im = mad_im > 0.f ? 1.0f / (mad_im * kMadScale) : 0.f;
+    const float2 x = d.x[j];
+    const float a = fmaf(x.x, inv_re, -med_re * inv_re);
+    const float c = fmaf(x.y, inv_im, -med_im * inv_im);
+    acc += fmaf(a, a, c * c);
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
 // Emit: pool entry f (tile, rank) goes to its canonical place, the tile's
 // exclusive prefix plus its rank, with its Gaussian-equivalent sigma.
@@ -158,13 +183,24 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
     }
     const SpecDesc &d = p.nspec > 1 ? p.descs[s] : single;
     const uint32_t w = (e.rank_width & ((1u << kWidthBits) - 1u)) + 1u;
-    const double lp = log_sf_chi2_even((double)e.power, w * d.dofmul) + log(d.ntrials);
+    double lp = log_sf_chi2_even((double)e.power, w * d.dofmul) + log(d.ntrials);
+    double sg = sigma_from_logp(lp < 0.0 ? lp : 0.0);
+    float pw = e.power;
+    bool keep = true;
+    if (p.fp16 && (sg < (double)p.sigma + kRecheckBand || !(pw < kRecheckPower))) {
+      // within the re-check band (or from saturated FP16 input): the FP32
+      // power decides
+      pw = power32_window(d, p.block, p.from_power, e.bin, w);
+      lp = log_sf_chi2_even((double)pw, w * d.dofmul) + log(d.ntrials);
+      sg = sigma_from_logp(lp < 0.0 ? lp : 0.0);
+      keep = sg >= (double)p.sigma;
+    }
     pulscan_candidate c;
     c.spectrum = d.spec_id;
     c.bin = p.rblock ? e.bin / p.rblock : e.bin;
     c.width = w;
-    c.power = e.power;
-    c.sigma = (float)sigma_from_logp(lp < 0.0 ? lp : 0.0);
+    c.power = pw;
+    c.sigma = keep ? (float)sg : NAN;
     c.chunk = e.bin / p.chunk;
     c.harmonics = d.harm;
     c.reserved = 0u;
@@ -179,60 +215,70 @@ hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t gri
 }
 
 // ---------------------------------------------------------------------------
-// Best candidate per (spectrum, stage, chunk).  The list is in canonical
-// order, so each key is one contiguous run.  One workgroup walks the list in
-// rounds of kBestThreads: a thread whose entry starts a run picks the run's
-// highest sigma (the first on ties) and writes it at its run rank.
+// Final pass over a canonical candidate list: drops the entries the FP32
+// re-check rejected (sigma NaN) and, with `best`, keeps of each (spectrum,
+// stage, chunk) only its highest-sigma entry (the first on ties).  Each key
+// is one contiguous run of the list.  One workgroup walks the list in rounds
+// of kFinThreads; ranks come from ballots, so the order is kept.
 
-constexpr int kBestThreads = 1024;
+constexpr int kFinThreads = 1024;
 
 __device__ __forceinline__ bool same_key(const pulscan_candidate &a, const pulscan_candidate &b) {
   return a.spectrum == b.spectrum && a.harmonics == b.harmonics && a.chunk == b.chunk;
 }
 
-__global__ __launch_bounds__(kBestThreads) void best_kernel(
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(
     const pulscan_candidate *__restrict__ all, const unsigned long long *__restrict__ total_p,
     uint64_t all_cap, pulscan_candidate *__restrict__ out, uint64_t capacity,
-    unsigned long long *count, unsigned long long *count2) {
-  __shared__ uint32_t wave_cnt[kBestThreads / 64];
+    unsigned long long *count, unsigned long long *count2, int best) {
+  __shared__ uint32_t wave_cnt[kFinThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long tot = *total_p;
   const uint64_t n = tot < all_cap ? tot : all_cap;
-  uint64_t runs = 0;
-  for (uint64_t base = 0; base < n; base += kBestThreads) {
+  uint64_t kept = 0;
+  for (uint64_t base = 0; base < n; base += kFinThreads) {
     const uint64_t i = base + tid;
-    bool head = false;
-    if (i < n) head = i == 0 || !same_key(all[i - 1], all[i]);
-    const unsigned long long mask = __ballot(head);
+    bool emit = false;
+    uint64_t pick = i;
+    if (i < n) {
+      if (!best) {
+        emit = !isnan(all[i].sigma);
+      } else if (i == 0 || !same_key(all[i - 1], all[i])) {
+        // run head: the best surviving entry of the run
+        for (uint64_t j = i; j < n && same_key(all[i], all[j]); ++j) {
+          if (isnan(all[j].sigma)) continue;
+          if (!emit || all[j].sigma > all[pick].sigma) pick = j;
+          emit = true;
+        }
+      }
+    }
+    const unsigned long long mask = __ballot(emit);
     if (lane == 0) wave_cnt[wave] = (uint32_t)__popcll(mask);
     __syncthreads();
     uint64_t before = 0, here = 0;
-    for (uint32_t v = 0; v < kBestThreads / 64; ++v) {
+    for (uint32_t v = 0; v < kFinThreads / 64; ++v) {
       before += v < wave ? wave_cnt[v] : 0u;
       here += wave_cnt[v];
     }
-    if (head) {
-      const uint64_t rank = runs + before + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
-      uint64_t b = i;
-      for (uint64_t j = i + 1; j < n && same_key(all[i], all[j]); ++j)
-        if (all[j].sigma > all[b].sigma) b = j;
-      if (rank < capacity) out[rank] = all[b];
+    if (emit) {
+      const uint64_t rank = kept + before + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
+      if (rank < capacity) out[rank] = all[pick];
     }
-    runs += here;
+    kept += here;
     __syncthreads();
   }
   if (tid == 0) {
-    *count = runs;
-    if (count2) *count2 = runs;
+    *count = kept;
+    if (count2) *count2 = kept;
   }
 }
 
-hipError_t launch_best(const pulscan_candidate *all, const unsigned long long *total,
-                       uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
-                       unsigned long long *count, unsigned long long *count2,
-                       hipStream_t stream) {
-  hipLaunchKernelGGL(best_kernel, dim3(1), dim3(kBestThreads), 0, stream, all, total, all_cap,
-                     out, capacity, count, count2);
+hipError_t launch_finalize(const pulscan_candidate *all, const unsigned long long *total,
+                           uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
+                           unsigned long long *count, unsigned long long *count2, int best,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, stream, all, total, all_cap,
+                     out, capacity, count, count2, best);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ from .spectra import (  # noqa: F401
     draw_tones,
     inject_tones,
     make_spectrum,
+    make_spectrum_device,
     red_ramp,
     rng_for,
     white_noise,

@@ -178,3 +178,38 @@ def batched_workload(nspec: int = 512, n_lo: int = 1 << 20, n_hi: int = 1 << 23,
         out.append(Workload(f"batch{seed}_{s}", n, z, 0, sigma, seed * 1000003 + s, k, None,
                             (1, 200), (5.0, 20.0), (1000, max(1001, n - 202))))
     return out
+
+
+def make_spectrum_device(wl: Workload, tone_power: Optional[ToneGen], device="cuda",
+                         nbins: Optional[int] = None):
+    """The same recipe as make_spectrum, generated on a GPU for batches too
+    large to build on the host: the N(0, 1) noise comes from torch's seeded
+    device generator (seed wl.seed), tone parameters and phases from the
+    numpy stream of make_spectrum.  The values differ from make_spectrum's;
+    a test that needs the oracle copies the spectrum back.  Returns a
+    float32 (n, 2) device tensor and the tones."""
+    import torch
+    rng = rng_for(wl.seed)
+    n = wl.nbins if nbins is None else int(nbins)
+    tones = draw_tones(rng, wl, nbins=n) if tone_power is not None else []
+    g = torch.Generator(device=device)
+    g.manual_seed(int(wl.seed))
+    x = torch.randn((n, 2), generator=g, device=device, dtype=torch.float32)
+    if wl.red_frac > 0:
+        K = int(np.floor(wl.red_frac * n))
+        if K > 0:
+            k = np.arange(K, dtype=np.float64)
+            sc = torch.from_numpy(np.sqrt(K / np.maximum(k, 1.0)).astype(np.float32)).to(device)
+            x[:K] *= sc[:, None]
+    if tones:
+        ntrials = float(n) * wl.zmax
+        for t in tones:
+            w = min(t.z + 1, wl.zmax)
+            T = float(tone_power(t.A, w, ntrials))
+            t.alpha2 = max(T - 2.0 * w, 0.0) / w
+            lo, hi = t.r0, min(t.r0 + t.z + 1, n)
+            phi = rng.uniform(0.0, 2.0 * np.pi, size=hi - lo)
+            amp = np.float32(np.sqrt(t.alpha2))
+            add = np.stack([amp * np.cos(phi), amp * np.sin(phi)], axis=1).astype(np.float32)
+            x[lo:hi] += torch.from_numpy(add).to(device)
+    return x, tones

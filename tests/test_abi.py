@@ -64,11 +64,13 @@ int main(void) {
          offsetof(pulscan_candidate, harmonics));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(pulscan_candidates, capacity), offsetof(pulscan_candidates, count),
          offsetof(pulscan_candidates, on_device), offsetof(pulscan_candidates, count_device), sizeof(pulscan_complex));
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_opts, norm), offsetof(pulscan_opts, norm_block),
+  printf("%zu %zu %zu %zu\\n", sizeof(pulscan_server_config), offsetof(pulscan_server_config, opts),
+         sizeof(pulscan_result), offsetof(pulscan_result, candidates));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", offsetof(pulscan_opts, norm), offsetof(pulscan_opts, norm_block),
          offsetof(pulscan_opts, ntrials), offsetof(pulscan_opts, width_search),
          offsetof(pulscan_opts, async), offsetof(pulscan_opts, stream), offsetof(pulscan_opts, dense),
          offsetof(pulscan_opts, numharm), offsetof(pulscan_opts, best_per_chunk),
-         offsetof(pulscan_opts, rblock));
+         offsetof(pulscan_opts, rblock), offsetof(pulscan_opts, graph), offsetof(pulscan_opts, power_fp16));
   return 0;
 }
 """)
@@ -86,12 +88,16 @@ int main(void) {
     S = pk.pulscan_candidates
     assert [int(v) for v in lines[2].split()] == [S.capacity.offset, S.count.offset,
                                                   S.on_device.offset, S.count_device.offset, 8]
+    assert [int(v) for v in lines[3].split()] == [
+        ctypes.sizeof(pk.pulscan_server_config), pk.pulscan_server_config.opts.offset,
+        ctypes.sizeof(pk.pulscan_result), pk.pulscan_result.candidates.offset]
     O = pk.pulscan_opts
-    assert [int(v) for v in lines[3].split()] == [O.norm.offset, O.norm_block.offset,
+    assert [int(v) for v in lines[4].split()] == [O.norm.offset, O.norm_block.offset,
                                                   O.ntrials.offset, O.width_search.offset,
                                                   O.async_.offset, O.stream.offset, O.dense.offset,
                                                   O.numharm.offset, O.best_per_chunk.offset,
-                                                  O.rblock.offset]
+                                                  O.rblock.offset, O.graph.offset,
+                                                  O.power_fp16.offset]
     assert [d[0] for d in pk.CANDIDATE_DTYPE.descr] == [f[0] for f in C._fields_]
 
 
@@ -103,8 +109,8 @@ def test_strerror_and_default_options(L):
     assert pk.pulscan_strerror(12345) == "unknown status"
     o = pk.pulscan_opts_default()
     assert (o.norm, o.norm_block, o.ntrials, o.width_search, o.async_, o.stream, o.dense,
-            o.numharm, o.best_per_chunk, o.rblock) == \
-        (pk.PULSCAN_NORM_MOM, 0, 0.0, pk.PULSCAN_W_ALL, 0, None, 0, 1, 0, 0)
+            o.numharm, o.best_per_chunk, o.rblock, o.graph, o.power_fp16) == \
+        (pk.PULSCAN_NORM_MOM, 0, 0.0, pk.PULSCAN_W_ALL, 0, None, 0, 1, 0, 0, 0, 0)
 
 
 def test_null_arguments_are_rejected_without_a_device(L):
@@ -124,6 +130,17 @@ def test_null_arguments_are_rejected_without_a_device(L):
     assert L.pulscan_ctx_kernel_time(None, ctypes.byref(ms), ctypes.byref(k)) == EINVAL
     assert L.pulscan_ctx_create(None, 0) == EINVAL
     L.pulscan_ctx_destroy(None)   # a no-op
+    cfg = pk.pulscan_server_config()
+    L.pulscan_server_config_default(ctypes.byref(cfg))
+    assert (cfg.hbm_budget, cfg.max_batch, cfg.chunk, cfg.sigma_thresh, cfg.max_candidates) == \
+        (4 << 30, 256, 1024, 6.0, 1 << 20)
+    assert L.pulscan_server_create(None, 0, ctypes.byref(cfg)) == EINVAL
+    assert L.pulscan_server_submit(None, None, 4096, 10, 1) == EINVAL
+    assert L.pulscan_server_poll(None, None, 0, 0) == EINVAL
+    assert L.pulscan_server_stats(None, None, None, None, None) == EINVAL
+    assert L.pulscan_host_alloc(None, 64) == EINVAL
+    L.pulscan_server_destroy(None)   # a no-op
+    L.pulscan_host_free(None)        # a no-op
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

@@ -169,3 +169,78 @@ def test_variant_options_are_validated(ctx, pk):
         with pytest.raises(pk.PulscanError) as e:
             ctx.pulscan_search_ex(d, 16, 256, 6.0, opts=o)
         assert e.value.status == pk.PULSCAN_EINVAL
+
+
+# ----------------------------------------------------- FP16 power storage --
+
+# FP16 storage rounds each power to 11 bits (relative 2^-11 = 4.9e-4); a
+# boxcar of them is within that of its FP32 sum, and the re-check makes every
+# decision within 0.5 sigma of the threshold on FP32 power.  The reported
+# power of a candidate is then within 1e-3 of the oracle's maximum (a
+# re-checked one is the FP32 power at the FP16 argmax, a near tie at most), its
+# sigma within 0.05, and the candidate sets differ at most in entries whose
+# oracle sigma is within 0.05 of the threshold.
+POWER16_RTOL = 1e-3
+SIGMA16_ATOL = 0.05
+BAND16 = 0.05
+
+
+def fp16_diff(got, orc, sigma, label):
+    g = {(int(c["harmonics"]), int(c["chunk"]), int(c["width"])): c for c in got}
+    o = {(int(c["harm"]), int(c["chunk"]), int(c["width"])): c for c in orc.cands}
+    only_o = set(o) - set(g)
+    only_g = set(g) - set(o)
+    for k in only_o:
+        assert abs(float(o[k]["sigma"]) - sigma) < BAND16, (label, "missing", k, o[k])
+    for k in only_g:
+        assert abs(float(g[k]["sigma"]) - sigma) < BAND16, (label, "extra", k, g[k])
+    rel = 0.0
+    for k in set(g) & set(o):
+        a, b = g[k], o[k]
+        r = abs(float(a["power"]) - b["power"]) / b["power"]
+        rel = max(rel, r)
+        assert r <= POWER16_RTOL, (label, k, a, b)
+        assert abs(float(a["sigma"]) - b["sigma"]) <= SIGMA16_ATOL, (label, k, a, b)
+    say(f"{label}: {len(g)} candidates, set difference {len(only_o)} missing / {len(only_g)} "
+        f"extra, max relative boxcar error {rel:.2e}")
+    return len(only_o), len(only_g), rel
+
+
+@pytest.mark.parametrize("nbins,Z,C,numharm", [(1 << 16, 64, 256, 1), (1 << 20, 200, 1024, 1),
+                                               (1 << 18, 64, 1024, 3)])
+def test_fp16_power_matches_oracle(ctx, pk, oracle_lib, nbins, Z, C, numharm):
+    wl = synth.workload("plain_2e23")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=nbins)
+    d = to_device(x)
+    got, n = ctx.pulscan_search_ex(d, Z, C, 6.0,
+                                   opts=pk.make_opts(power_fp16=True, numharm=numharm))
+    assert n == len(got) > 0
+    keys = [(int(c["harmonics"]), int(c["chunk"]), int(c["width"])) for c in got]
+    assert keys == sorted(keys)
+    orc = oracle_lib.search(x, Z, C, 6.0, numharm=numharm)
+    fp16_diff(got, orc, 6.0, f"fp16 n={nbins} numharm={numharm}")
+
+
+def test_fp16_pruned_equals_dense_and_batched(ctx, pk, oracle_lib):
+    wl = synth.workload("plain_2e16")
+    xs = [synth.make_spectrum(wl, oracle_lib.power_for_sigma, spawn=s, nbins=n)[0]
+          for s, n in ((0, 1 << 16), (1, 50000))]
+    ds = [to_device(x) for x in xs]
+    a, na = ctx.pulscan_search_ex(ds[0], 64, 256, 6.0, opts=pk.make_opts(power_fp16=True))
+    b, nb = ctx.pulscan_search_ex(ds[0], 64, 256, 6.0,
+                                  opts=pk.make_opts(power_fp16=True, dense=True))
+    assert na == nb and (a == b).all()
+    got, n, _ = ctx.pulscan_search_batched(ds, [64, 48], 256, 6.0,
+                                           opts=pk.make_opts(power_fp16=True))
+    c, _ = ctx.pulscan_search_ex(ds[1], 48, 256, 6.0, opts=pk.make_opts(power_fp16=True))
+    c["spectrum"] = 1
+    ref = np.concatenate([a, c])
+    assert n == len(ref) and (got == ref).all()
+
+
+def test_fp16_unsupported_with_4096_blocks(ctx, pk):
+    import torch
+    d = torch.zeros((1 << 14, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(pk.PulscanError) as e:
+        ctx.pulscan_search_ex(d, 64, 4096, 6.0, opts=pk.make_opts(power_fp16=True))
+    assert e.value.status == pk.PULSCAN_EUNSUPPORTED
