@@ -108,10 +108,12 @@ typedef struct {
 
 /* Options of the _ex and batched calls (fill with pulscan_opts_default). */
 typedef struct {
-  int32_t norm;         /* PULSCAN_NORM_MOM (default): median of medians; the GPU
-                           kernels support 4^k blocks of 64..4096 bins.
-                           PULSCAN_NORM_EXACT: exact median/MAD (not yet on GPU:
-                           PULSCAN_EUNSUPPORTED)                                   */
+  int32_t norm;         /* PULSCAN_NORM_MOM (default): median of medians (section
+                           2.5); the GPU kernels support 4^k blocks of 64..4096
+                           bins.  PULSCAN_NORM_EXACT: the exact median and MAD
+                           (mean of the two middle values) of the CPU version,
+                           by a radix select; blocks of 64, 256 or 1024 bins,
+                           several times the normalisation work of MoM          */
   int32_t norm_block;   /* normalisation block in bins; 0 = chunk                    */
   double ntrials;       /* Bonferroni trials; 0 = nbins * searched widths            */
   int32_t width_search; /* PULSCAN_W_ALL (default): widths 1..zmax.

@@ -178,9 +178,10 @@ int check_spectrum(const void *x, uint64_t n, int zmax, int chunk, const pulscan
   const uint64_t B = o.norm_block > 0 ? (uint64_t)o.norm_block : (uint64_t)chunk;
   if (n < B || n < (uint64_t)zmax) return PULSCAN_EINVAL;
   if (o.norm == PULSCAN_NORM_MOM && !is_pow4(B)) return PULSCAN_EINVAL;
-  if (o.norm == PULSCAN_NORM_EXACT) return PULSCAN_EUNSUPPORTED;
+  // the kernels hold a block as 64 lanes x {1, 4, 16, 64} values
+  if (o.norm == PULSCAN_NORM_EXACT && (!is_pow4(B) || B > 1024)) return PULSCAN_EUNSUPPORTED;
   if (B < 64 || B > 4096) return PULSCAN_EUNSUPPORTED;
-  if (o.power_fp16 && B == 4096) return PULSCAN_EUNSUPPORTED;
+  if (o.power_fp16 && (B == 4096 || o.norm == PULSCAN_NORM_EXACT)) return PULSCAN_EUNSUPPORTED;
   if (chunk % 64 != 0 || chunk > kMaxTile) return PULSCAN_EUNSUPPORTED;
   const uint64_t nchunks = (n + chunk - 1) / chunk;
   if (nchunks * (uint64_t)zmax >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
@@ -357,6 +358,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   bp.mode = search ? kModeSearch : power_only ? kModePower : kModeTables;
   bp.from_power = a.from_power ? 1 : 0;
   bp.dense = a.opts.dense ? 1 : 0;
+  bp.norm_exact = a.opts.norm == PULSCAN_NORM_EXACT ? 1 : 0;
   bp.M = a.M;
   bp.I = a.I;
   bp.P_out = a.P_out;

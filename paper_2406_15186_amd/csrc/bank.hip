@@ -3,7 +3,8 @@
 // maxima with the threshold test.
 //
 //  * Normalisation (section 2.2.3; section 2.5 and the appendix algorithm
-//    "Median of Medians Normalisation"): one wave per block of B = 64*EPL bins.
+//    "Median of Medians Normalisation", or the exact median of the CPU
+//    version by a radix select): one wave per block of B = 64*EPL bins.
 //    Lane l holds elements l + 64m, so the first levels of the median-of-4
 //    tree (strides B/4, B/16, ... down to 64) stay inside a lane and the last
 //    three (16, 4, 1 lanes) use cross-lane moves (permlane swaps and DPP row
@@ -157,6 +158,70 @@ __device__ __forceinline__ float unord_f32(uint32_t o) {
   const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
   return __uint_as_float(u);
 }
+__device__ __forceinline__ float unord_key(uint32_t o) { return unord_f32(o); }
+
+// Exact median of the 64*EPL values f(a[m]) of one wave (lane l holds
+// element l + 64m), f(x) = x or |x - c| for DEV: the mean of the two middle
+// order statistics (the CPU version's median, section 2.5).  The lower one
+// is found by a binary radix select on the order-preserving 32-bit keys,
+// most significant bit first, counting with wave-wide sums; the upper one is
+// the same value when it repeats, else the smallest key above it.
+template <int EPL, bool DEV>
+__device__ __forceinline__ uint32_t key_of(const float (&a)[EPL], int m, float c) {
+  const float v = DEV ? fabsf(a[m] - c) : a[m];
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int EPL, bool DEV>
+__device__ __forceinline__ float wave_median_exact(const float (&a)[EPL], float c) {
+  constexpr uint32_t N = 64u * EPL;
+  const uint32_t k = N / 2 - 1;  // rank (0-based) of the lower middle value
+  uint32_t key[EPL];
+#pragma unroll
+  for (int m = 0; m < EPL; ++m) key[m] = key_of<EPL, DEV>(a, m, c);
+  uint32_t prefix = 0, rank = k;
+#pragma unroll 1
+  for (int bit = 31; bit >= 0; --bit) {
+    const uint32_t hi = bit == 31 ? 0u : (0xFFFFFFFFu << (bit + 1));
+    const uint32_t b = 1u << bit;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) cnt += ((key[m] & hi) == prefix && !(key[m] & b)) ? 1u : 0u;
+    cnt = wave_sum_u32(cnt);
+    if (rank >= cnt) {
+      rank -= cnt;
+      prefix |= b;
+    }
+  }
+  // prefix is the key of the k-th smallest; the (k+1)-th is equal to it when
+  // more than k + 1 keys are <= it, else the least key above it
+  uint32_t le = 0, above = 0xFFFFFFFFu;
+#pragma unroll
+  for (int m = 0; m < EPL; ++m) {
+    le += key[m] <= prefix ? 1u : 0u;
+    if (key[m] > prefix) above = min(above, key[m]);
+  }
+  le = wave_sum_u32(le);
+  above = wave_min_u32(above);
+  const uint32_t k2 = le >= k + 2 ? prefix : above;
+  const float v1 = unord_key(prefix), v2 = unord_key(k2);
+  const float med = 0.5f * (v1 + v2);
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(med)));
+}
+
 
 // LDS address of tile-relative bin i.  Bins are grouped in segments of 64*K;
 // within a segment, bin L*K + j (lane L, j < K) sits at row j, column L of a
@@ -222,7 +287,7 @@ __device__ __forceinline__ void load_block(const float2 *__restrict__ x, uint32_
 // Normalise a loaded block and write its power into the tile's LDS array for
 // every bin of the block that the tile needs (tile-relative index below
 // `need`).  Executed by one whole wave.
-template <int K, int EPL, typename PT>
+template <int K, int EPL, typename PT, bool EXACT>
 __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, uint32_t t0,
                                                 uint32_t need, uint32_t T, PT *Pl,
                                                 uint32_t lane, float *P_out, float *stats_out) {
@@ -232,7 +297,13 @@ __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, 
   float(&im)[EPL] = bd.im;
   const uint32_t own = bd.own, s0 = bd.s0;
   float med_re, med_im, mad_re, mad_im;
-  if constexpr (EPL >= 16) {
+  if constexpr (EXACT) {
+    // the exact median and MAD
+    med_re = wave_median_exact<EPL, false>(re, 0.f);
+    med_im = wave_median_exact<EPL, false>(im, 0.f);
+    mad_re = wave_median_exact<EPL, true>(re, med_re);
+    mad_im = wave_median_exact<EPL, true>(im, med_im);
+  } else if constexpr (EPL >= 16) {
     med_re = wave_mom1<EPL, false>(re, 0.f);
     med_im = wave_mom1<EPL, false>(im, 0.f);
     mad_re = wave_mom1<EPL, true>(re, med_re);
@@ -600,14 +671,15 @@ constexpr int threads_for() {
   return EPL >= 64 ? 256 : kMaxThreads;  // 4096-bin blocks need the whole register file
 }
 // Waves per SIMD the register allocation must allow: 6 lets three 8-wave
-// workgroups share a CU.
-template <int EPL>
+// workgroups share a CU.  The exact median keeps a block's keys in
+// registers and settles for two.
+template <int EPL, bool EXACT>
 constexpr int waves_per_eu_for() {
-  return EPL >= 64 ? 1 : 6;
+  return EPL >= 64 ? 1 : EXACT ? 4 : 6;
 }
 
-template <int K, int EPL, typename PT>
-__global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void bank_kernel(
+template <int K, int EPL, typename PT, bool EXACT>
+__global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>())) void bank_kernel(
     BankParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ uint32_t wave_sum[kMaxThreads / 64];
@@ -720,7 +792,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), waves_per_eu_for<EPL>()) void b
       float *so = dbg ? p.stats_out : (p.mode == kModeSearch && sizeof(PT) == 2) ? d.aux : nullptr;
       for (uint32_t b = bfirst + wave; b <= blast; b += nw) {
         if (b != bfirst + wave) load_block<EPL>(d.x, n, b, lane, bd);
-        normalise_block<K, EPL, PT>(bd, b, t0, need, T, Pl, lane, po, so);
+        normalise_block<K, EPL, PT, EXACT>(bd, b, t0, need, T, Pl, lane, po, so);
       }
     }
     }
@@ -975,18 +1047,18 @@ std::vector<uint32_t> tile_choices(uint32_t C, uint32_t B, uint32_t zmax_max, bo
   return out;
 }
 
-template <int K, typename PT>
+template <int K, typename PT, bool EXACT>
 static hipError_t launch_k(int EPL, uint64_t grid, uint32_t threads, size_t lds,
                            const BankParams &p, hipStream_t stream) {
   const dim3 gd((uint32_t)grid), bd(threads);
   switch (EPL) {
-    case 1: hipLaunchKernelGGL((bank_kernel<K, 1, PT>), gd, bd, lds, stream, p); break;
-    case 4: hipLaunchKernelGGL((bank_kernel<K, 4, PT>), gd, bd, lds, stream, p); break;
-    case 16: hipLaunchKernelGGL((bank_kernel<K, 16, PT>), gd, bd, lds, stream, p); break;
+    case 1: hipLaunchKernelGGL((bank_kernel<K, 1, PT, EXACT>), gd, bd, lds, stream, p); break;
+    case 4: hipLaunchKernelGGL((bank_kernel<K, 4, PT, EXACT>), gd, bd, lds, stream, p); break;
+    case 16: hipLaunchKernelGGL((bank_kernel<K, 16, PT, EXACT>), gd, bd, lds, stream, p); break;
     case 64:
-      // 4096-bin blocks keep FP32 power only
-      if (sizeof(PT) != 4) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((bank_kernel<K, 64, float>), gd, bd, lds, stream, p);
+      // 4096-bin blocks: FP32 power and the median of medians only
+      if (sizeof(PT) != 4 || EXACT) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((bank_kernel<K, 64, float, false>), gd, bd, lds, stream, p);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -996,8 +1068,13 @@ static hipError_t launch_k(int EPL, uint64_t grid, uint32_t threads, size_t lds,
 template <int K>
 static hipError_t launch_pt(const Geometry &g, const BankParams &p, uint64_t grid,
                             uint32_t threads, hipStream_t stream) {
-  return g.fp16 ? launch_k<K, _Float16>(g.EPL, grid, threads, g.lds_bytes, p, stream)
-                : launch_k<K, float>(g.EPL, grid, threads, g.lds_bytes, p, stream);
+  if (p.norm_exact) {
+    // the exact median keeps FP32 power
+    if (g.fp16) return hipErrorInvalidValue;
+    return launch_k<K, float, true>(g.EPL, grid, threads, g.lds_bytes, p, stream);
+  }
+  return g.fp16 ? launch_k<K, _Float16, false>(g.EPL, grid, threads, g.lds_bytes, p, stream)
+                : launch_k<K, float, false>(g.EPL, grid, threads, g.lds_bytes, p, stream);
 }
 
 hipError_t launch_bank(const Geometry &g, const BankParams &p, uint64_t grid, hipStream_t stream) {

@@ -70,6 +70,7 @@ struct BankParams {
   int mode;                // BankMode
   int from_power;          // x holds float power; skip normalisation
   int dense;               // 1: skip the pruning bound (every width block evaluated)
+  int norm_exact;          // 1: exact median / MAD instead of the median of medians
   // search mode: candidate staging and the scan of the per-tile counts,
   // which the workgroup that finishes last performs
   StageEntry *pool;        // staging pool

@@ -295,7 +295,6 @@ int pulscan_server_create(pulscan_server **out, int device, const pulscan_server
       cfg->max_candidates < 1 || !(cfg->sigma_thresh == cfg->sigma_thresh))
     return PULSCAN_EINVAL;
   if (cfg->opts.async || cfg->opts.graph || cfg->opts.stream) return PULSCAN_EINVAL;
-  if (cfg->opts.norm != PULSCAN_NORM_MOM) return PULSCAN_EUNSUPPORTED;
   pulscan_server *s = new (std::nothrow) pulscan_server();
   if (!s) return PULSCAN_ENOMEM;
   s->device = device;

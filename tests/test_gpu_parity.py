@@ -214,8 +214,10 @@ def test_invalid_arguments(ctx, pk):
         (dict(zmax=10, chunk=8192), pk.PULSCAN_EINVAL),               # block > nbins
         (dict(zmax=10, chunk=128), pk.PULSCAN_EINVAL),                # MoM block not 4^k
         (dict(zmax=10, chunk=100, opts=pk.make_opts(norm_block=64)), pk.PULSCAN_EUNSUPPORTED),
-        (dict(zmax=10, chunk=256, opts=pk.make_opts(norm=pk.PULSCAN_NORM_EXACT)),
-         pk.PULSCAN_EUNSUPPORTED),
+        (dict(zmax=10, chunk=4096, opts=pk.make_opts(norm=pk.PULSCAN_NORM_EXACT)),
+         pk.PULSCAN_EUNSUPPORTED),                                    # exact: blocks <= 1024
+        (dict(zmax=10, chunk=512, opts=pk.make_opts(norm=pk.PULSCAN_NORM_EXACT)),
+         pk.PULSCAN_EUNSUPPORTED),                                    # exact: 64 lanes x 4^k
         (dict(zmax=10, chunk=16), pk.PULSCAN_EUNSUPPORTED),           # valid 4^k, below 64
         (dict(zmax=10, chunk=256, opts=pk.make_opts(ntrials=0.5)), pk.PULSCAN_EINVAL),
         (dict(zmax=10, chunk=256, opts=pk.make_opts(width_search=7)), pk.PULSCAN_EINVAL),

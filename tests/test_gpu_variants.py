@@ -244,3 +244,54 @@ def test_fp16_unsupported_with_4096_blocks(ctx, pk):
     with pytest.raises(pk.PulscanError) as e:
         ctx.pulscan_search_ex(d, 64, 4096, 6.0, opts=pk.make_opts(power_fp16=True))
     assert e.value.status == pk.PULSCAN_EUNSUPPORTED
+
+
+# ------------------------------------------- exact median normalisation --
+
+@pytest.mark.parametrize("n,Z,C", [(1 << 16, 64, 256), (65536 + 100, 64, 256), (1 << 14, 200, 1024),
+                                   (1 << 12, 32, 64)])
+def test_exact_normalisation_tables(ctx, pk, oracle_lib, n, Z, C):
+    """Exact median / MAD per block (the CPU version's, section 2.5) against
+    the oracle's EXACT mode: statistics, normalised power and the dense
+    per-chunk maxima."""
+    from gpu_helpers import compare_tables
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=n)
+    opts = pk.make_opts(norm=pk.PULSCAN_NORM_EXACT)
+    M, I, P, S = ctx.pulscan_debug_tables(to_device(x), Z, C, opts=opts)
+    _, _, st = oracle_lib.normalise(x, C, oracle_lib.NORM_EXACT)
+    np.testing.assert_allclose(S.cpu().numpy().astype(np.float64), st, rtol=2e-6, atol=1e-6)
+    orc = oracle_lib.search(x, Z, C, 6.0, mode=oracle_lib.NORM_EXACT, tables=True)
+    np.testing.assert_allclose(P.cpu().numpy().astype(np.float64), orc.P, rtol=1e-5, atol=1e-5)
+    err, ties = compare_tables(M.cpu().numpy(), I.cpu().numpy(), orc.M, orc.I, orc.P, "exact")
+    say(f"exact tables n={n}: max rel err {err:.2e}, near ties {ties}")
+
+
+def test_exact_median_with_repeated_values(ctx, pk, oracle_lib):
+    """Blocks full of ties (quantised amplitudes) and constant blocks (MAD 0)."""
+    rng = np.random.default_rng(12)
+    n = 1 << 14
+    x = np.round(rng.standard_normal((n, 2)) * 2).astype(np.float32) / 2
+    x[1024:2048] = 3.0
+    x[5000:5300, 0] = -1.5
+    xc = x.view(np.complex64).reshape(n)
+    opts = pk.make_opts(norm=pk.PULSCAN_NORM_EXACT)
+    M, I, P, S = ctx.pulscan_debug_tables(to_device(xc), 16, 256, opts=opts)
+    _, _, st = oracle_lib.normalise(xc, 256, oracle_lib.NORM_EXACT)
+    np.testing.assert_array_equal(S.cpu().numpy().astype(np.float64), st)
+    orc = oracle_lib.search(xc, 16, 256, 6.0, mode=oracle_lib.NORM_EXACT, tables=True)
+    np.testing.assert_allclose(P.cpu().numpy().astype(np.float64), orc.P, rtol=1e-5, atol=1e-5)
+
+
+def test_exact_search_matches_oracle(ctx, pk, oracle_lib):
+    wl = synth.workload("plain_2e16")
+    x, tones = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    d = to_device(x)
+    got, n = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(norm=pk.PULSCAN_NORM_EXACT))
+    orc = oracle_lib.search(x, 64, 256, 6.0, mode=oracle_lib.NORM_EXACT, tables=True)
+    compare_candidates(got, orc, orc.P, float(len(x) * 64), 6.0, oracle_lib, "exact search")
+    # every injected tone is found with the exact median (unlike the MoM,
+    # whose statistics a wide tone inflates)
+    for t in tones:
+        near = got[(got["bin"] >= t.r0 - t.z - 1) & (got["bin"] <= t.r0 + t.z + 1)]
+        assert len(near) > 0, t
