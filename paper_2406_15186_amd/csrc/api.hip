@@ -41,6 +41,7 @@ struct pulscan_ctx {
   DevBuf allbuf, hpow, hsum, hjobs;  // best-per-chunk scratch; harmonic power, sums, jobs
   DevBuf tune_out;                   // autotuner: candidate output of its timing runs
   DevBuf stats;                      // FP16 search: per-block statistics for the re-check
+  DevBuf span_sum, span_prefix;      // two-level scan of many tiles
   ThrKey thr_key;
   // what the device holds for batched launches (re-uploaded only on change)
   std::vector<ThreshJob> last_jobs;
@@ -63,6 +64,8 @@ struct pulscan_ctx {
   hipEvent_t pinned_ev = nullptr;
   bool pinned_pending = false;
   std::vector<SpecDesc> last_descs;  // what the device descriptor table holds
+  DevBuf pdescs;                     // descriptor table of the power pass (harmonic mode)
+  std::vector<SpecDesc> last_pdescs;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -81,7 +84,13 @@ struct Counters {
   uint32_t done;
   uint32_t gen;             // generation tag of the last launch's tile words
   unsigned long long best;  // candidates kept by the final pass (best / re-check)
+  uint32_t lost;            // two-level scan: a tile's count was missing
+  uint32_t pad;
 };
+
+// Launches with more tiles than this scan their counts in two kernels after
+// the bank kernel instead of in its last workgroup.
+constexpr uint64_t kInKernelScanMax = 4096;
 
 #define HIP_TRY(call)                       \
   do {                                      \
@@ -392,19 +401,31 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     bp.total = &cnt->total;
     bp.total2 = fin ? nullptr : reinterpret_cast<unsigned long long *>(a.out->count_device);
     bp.overflow = &cnt->overflow;
+    bp.scan_in_kernel = tiles <= kInKernelScanMax ? 1 : 0;
+    if (!bp.scan_in_kernel) {
+      const uint64_t nspan = (tiles + kScanSpan - 1) / kScanSpan;
+      st = grow(ctx, ctx->span_sum, nspan * sizeof(uint32_t), false);
+      if (st) return st;
+      st = grow(ctx, ctx->span_prefix, nspan * sizeof(uint32_t), false);
+      if (st) return st;
+    }
   }
 
   if (nspec > 1) {
-    const bool same = ctx->last_descs.size() == descs.size() &&
-                      memcmp(ctx->last_descs.data(), descs.data(), descs.size() * sizeof(SpecDesc)) == 0;
+    // the power pass of harmonic mode keeps its own table, so that a call
+    // repeating an earlier one re-uploads neither
+    DevBuf &buf = power_only ? ctx->pdescs : ctx->descs;
+    std::vector<SpecDesc> &last = power_only ? ctx->last_pdescs : ctx->last_descs;
+    const bool same = last.size() == descs.size() &&
+                      memcmp(last.data(), descs.data(), descs.size() * sizeof(SpecDesc)) == 0;
     if (!same) {
-      st = grow(ctx, ctx->descs, descs.size() * sizeof(SpecDesc), false);
+      st = grow(ctx, buf, descs.size() * sizeof(SpecDesc), false);
       if (st) return st;
-      st = upload(ctx, ctx->descs.p, descs.data(), descs.size() * sizeof(SpecDesc), stream);
+      st = upload(ctx, buf.p, descs.data(), descs.size() * sizeof(SpecDesc), stream);
       if (st) return st;
-      ctx->last_descs = descs;
+      last = descs;
     }
-    bp.descs = static_cast<const SpecDesc *>(ctx->descs.p);
+    bp.descs = static_cast<const SpecDesc *>(buf.p);
   }
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -420,6 +441,23 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     ctx->ev_rec.emplace_back(e0, e1);
   }
   if (!search) return PULSCAN_OK;
+  if (!bp.scan_in_kernel) {
+    BigScan bs{};
+    bs.tile_word = bp.tile_word;
+    bs.tile_prefix = bp.tile_prefix;
+    bs.span_sum = static_cast<uint32_t *>(ctx->span_sum.p);
+    bs.span_prefix = static_cast<uint32_t *>(ctx->span_prefix.p);
+    bs.total_tiles = tiles;
+    bs.gen = bp.gen;
+    bs.pool_head = bp.pool_head;
+    bs.done = bp.done;
+    bs.pool_cap = pool_cap;
+    bs.total = bp.total;
+    bs.total2 = bp.total2;
+    bs.overflow = bp.overflow;
+    bs.lost = &cnt->lost;
+    HIP_TRY(launch_scan_big(bs, stream));
+  }
 
   // emit into the caller's device buffer, or into ours for a host copy; with
   // best_per_chunk everything goes to scratch first
@@ -438,6 +476,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   ep.pool = bp.pool;
   ep.pool_cap = pool_cap;
   ep.tile_prefix = bp.tile_prefix;
+  ep.span_prefix = bp.scan_in_kernel ? nullptr : static_cast<const uint32_t *>(ctx->span_prefix.p);
   ep.total = bp.total;
   ep.chunk = a.chunk;
   ep.rblock = (uint32_t)a.opts.rblock;
@@ -628,6 +667,12 @@ int run_graph(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs 
     if (st || ce != hipSuccess) {
       (void)hipGetLastError();
       if (graph) (void)hipGraphDestroy(graph);
+      // captured work never ran: forget what it would have put on the device
+      ctx->last_jobs.clear();
+      ctx->last_descs.clear();
+      ctx->last_pdescs.clear();
+      ctx->last_hjobs.clear();
+      ++ctx->epoch;
       return st ? st : PULSCAN_EHIP;
     }
     const hipError_t ie = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
@@ -824,7 +869,8 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
   DevBuf *bufs[] = {&ctx->thr,    &ctx->pool,   &ctx->tile_word, &ctx->tile_prefix,
                     &ctx->counters, &ctx->outbuf, &ctx->descs,  &ctx->jobs,
                     &ctx->allbuf, &ctx->hpow,   &ctx->hsum,     &ctx->hjobs,
-                    &ctx->tune_out, &ctx->stats};
+                    &ctx->tune_out, &ctx->stats,  &ctx->pdescs,
+                    &ctx->span_sum, &ctx->span_prefix};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);

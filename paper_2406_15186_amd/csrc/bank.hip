@@ -755,7 +755,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
       // has published its count; taking the ticket now hides its latency
       // behind the spectrum loads
       if (p.mode == kModeSearch) {
-        ticket = atomicAdd(p.done, 1u);
+        if (p.scan_in_kernel) ticket = atomicAdd(p.done, 1u);
         gen = __hip_atomic_load(p.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
         if (gen == 0u) gen = 1u;  // words start at generation 0
       }
@@ -910,7 +910,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
         __builtin_amdgcn_s_waitcnt(0);
         __hip_atomic_store(p.tile_word + tg, ((unsigned long long)gen << 32) | tot,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = ticket == (uint32_t)(p.total_tiles - 1) ? 1u : 0u;
+        is_last = p.scan_in_kernel && ticket == (uint32_t)(p.total_tiles - 1) ? 1u : 0u;
         launch_gen = gen;
         lost_any = 0u;
       }
@@ -1088,6 +1088,98 @@ hipError_t launch_bank(const Geometry &g, const BankParams &p, uint64_t grid, hi
     case 16: return launch_pt<16>(g, p, grid, threads, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Two-level scan of the per-tile counts of launches with many tiles.
+
+constexpr int kBigThreads = 512;
+
+__global__ __launch_bounds__(kBigThreads) void scan_span_kernel(BigScan s) {
+  __shared__ uint32_t wave_sum[kBigThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t gen = __hip_atomic_load(s.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+  const uint32_t want = gen ? gen : 1u;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanSpan;
+  constexpr uint32_t PER = kScanSpan / kBigThreads;
+  uint32_t v[PER];
+  uint32_t mine = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; ++k) {
+    const uint64_t i = base + (uint64_t)tid * PER + k;
+    uint32_t c = 0;
+    if (i < s.total_tiles) {
+      const unsigned long long w = s.tile_word[i];  // written by the previous kernel
+      c = (uint32_t)(w >> 32) == want ? (uint32_t)w : 0u;
+      if ((uint32_t)(w >> 32) != want) atomicOr(s.lost, 1u);
+    }
+    v[k] = c;
+    mine += c;
+  }
+  uint32_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += t;
+  }
+  if (lane == 63) wave_sum[wave] = incl;
+  __syncthreads();
+  uint32_t run = 0, tot = 0;
+  for (uint32_t w = 0; w < kBigThreads / 64; ++w) {
+    run += w < wave ? wave_sum[w] : 0u;
+    tot += wave_sum[w];
+  }
+  run += incl - mine;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; ++k) {
+    const uint64_t i = base + (uint64_t)tid * PER + k;
+    if (i < s.total_tiles) s.tile_prefix[i] = run;
+    run += v[k];
+  }
+  if (tid == 0) s.span_sum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBigThreads) void scan_top_kernel(BigScan s, uint32_t nspan) {
+  __shared__ uint32_t wave_sum[kBigThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nspan; b0 += kBigThreads) {
+    const uint32_t i = b0 + tid;
+    const uint32_t v = i < nspan ? s.span_sum[i] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o, 64);
+      if (lane >= (uint32_t)o) incl += t;
+    }
+    if (lane == 63) wave_sum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (uint32_t w = 0; w < kBigThreads / 64; ++w) {
+      before += w < wave ? wave_sum[w] : 0u;
+      tot += wave_sum[w];
+    }
+    if (i < nspan) s.span_prefix[i] = carry + before + incl - v;
+    carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *s.total = carry;
+    if (s.total2) *s.total2 = carry;
+    *s.overflow = *s.lost ? 2u : (carry > s.pool_cap ? 1u : 0u);
+    *s.lost = 0u;
+    const uint32_t g = *s.gen + 1u;
+    *s.gen = g ? g : 1u;
+    *s.pool_head = 0u;
+    *s.done = 0u;
+  }
+}
+
+hipError_t launch_scan_big(const BigScan &s, hipStream_t stream) {
+  const uint32_t nspan = (uint32_t)((s.total_tiles + kScanSpan - 1) / kScanSpan);
+  hipLaunchKernelGGL(scan_span_kernel, dim3(nspan), dim3(kBigThreads), 0, stream, s);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kBigThreads), 0, stream, s, nspan);
+  return hipGetLastError();
 }
 
 }  // namespace pulscan

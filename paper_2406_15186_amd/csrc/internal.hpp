@@ -83,6 +83,7 @@ struct BankParams {
   unsigned long long *total;   // candidate count (device)
   unsigned long long *total2;  // optional second destination (the caller's)
   uint32_t *overflow;      // 1: the pool was too small; 2: a tile's count never arrived
+  int scan_in_kernel;      // 1: the last tile scans the counts; 0: launch_scan_big does
   float *M;                // tables mode: nchunks x zmax (spectrum 0 only)
   uint32_t *I;
   float *P_out;            // tables mode, optional: normalised power
@@ -132,6 +133,30 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
                              uint32_t zc_max, double sigma, int width_search, int debug,
                              hipStream_t stream);
 
+// Scan of the per-tile counts for launches with many tiles (batches), in
+// two kernels after the bank kernel: each workgroup scans kScanSpan tiles
+// into tile_prefix (relative to its span) and writes the span's total; one
+// workgroup scans the span totals into span_prefix, records the total and
+// the overflow flag, and re-arms the pool head, the finished-tile counter
+// and the generation.
+constexpr uint32_t kScanSpan = 4096;
+struct BigScan {
+  const unsigned long long *tile_word;
+  uint32_t *tile_prefix;
+  uint32_t *span_sum;
+  uint32_t *span_prefix;
+  uint64_t total_tiles;
+  uint32_t *gen;                   // the bank launch's generation is *gen + 1
+  uint32_t *pool_head;
+  uint32_t *done;
+  uint32_t pool_cap;
+  unsigned long long *total;
+  unsigned long long *total2;
+  uint32_t *overflow;
+  uint32_t *lost;                  // set by a span that found a count missing
+};
+hipError_t launch_scan_big(const BigScan &s, hipStream_t stream);
+
 // Candidate f of the staging pool goes to out[tile_prefix[tile] + rank]
 // (when that is below capacity), with its FP64 significance.
 struct EmitParams {
@@ -140,6 +165,7 @@ struct EmitParams {
   const StageEntry *pool;
   uint32_t pool_cap;
   const uint32_t *tile_prefix;
+  const uint32_t *span_prefix;     // non-null: tile_prefix is relative to its kScanSpan span
   const unsigned long long *total;
   uint32_t chunk;
   uint32_t rblock;                 // > 0: report bin / rblock

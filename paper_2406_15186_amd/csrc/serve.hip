@@ -49,6 +49,7 @@ struct Slot {
   int32_t status = PULSCAN_OK;
   double t_start = 0.0;
   bool busy = false;
+  bool in_ring = false;   // some spectrum of the set was copied into the ring
   uint64_t ring_end = 0;  // ring head after this set's copies
 };
 
@@ -177,7 +178,9 @@ void collect(pulscan_server *s) {
     uint64_t bytes = 0;
     for (const Request &r : sl.reqs) bytes += r.bytes;
     s->budget_used -= bytes;
-    ring_release_to(s, sl.ring_end);
+    // only sets that placed copies in the ring free ring space: a set of
+    // device spectra may have recorded a head from before the ring was reset
+    if (sl.in_ring) ring_release_to(s, sl.ring_end);
     for (auto &d : out) s->done.push_back(std::move(d));
     s->completed += sl.reqs.size();
   }
@@ -207,6 +210,8 @@ void work(pulscan_server *s) {
     if (!set.empty()) {
       Slot &sl = s->slots[s->next_slot];
       sl.busy = true;
+      sl.in_ring = false;
+      for (const Request &r : set) sl.in_ring = sl.in_ring || !r.on_device;
       sl.reqs = std::move(set);
       sl.ring_end = s->ring_head;
       sl.t_start = now_s(s->t0);

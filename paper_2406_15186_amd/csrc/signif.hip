@@ -167,7 +167,8 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
   const uint64_t stride = (uint64_t)gridDim.x * kEmitThreads;
   for (uint64_t f = (uint64_t)blockIdx.x * kEmitThreads + threadIdx.x; f < lim; f += stride) {
     const StageEntry e = p.pool[f];
-    const uint64_t dest = (uint64_t)p.tile_prefix[e.tile] + (e.rank_width >> kWidthBits);
+    const uint64_t dest = (uint64_t)p.tile_prefix[e.tile] + (e.rank_width >> kWidthBits) +
+                          (p.span_prefix ? p.span_prefix[e.tile / kScanSpan] : 0u);
     if (dest >= p.capacity) continue;
     int s = 0;
     if (p.nspec > 1) {

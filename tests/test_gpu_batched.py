@@ -113,11 +113,14 @@ def test_autotuned_chunk_is_reported_and_consistent(ctx, pk, oracle_lib):
     say(f"autotuned chunk {used}, {n} candidates")
 
 
-def test_dm_trial_batch_sampled_parity(ctx, pk, oracle_lib):
+@pytest.mark.parametrize("chunk", [1024, 256])
+def test_dm_trial_batch_sampled_parity(ctx, pk, oracle_lib, chunk):
     """A batch of 64 DM-trial spectra of 2^16..2^19 bins with per-spectrum zmax
     in {64, 128, 200} and 0-5 tones each (the batched workload's recipe at a
     size the oracle checks quickly), searched in one launch; three spectra
-    are compared with the oracle and all spectra's candidates are ordered."""
+    are compared with the oracle and all spectra's candidates are ordered.
+    With chunk 256 the batch has more than 4096 tiles, so the counts are
+    scanned by the two-level scan after the bank kernel."""
     wls = synth.batched_workload(nspec=64, n_lo=1 << 16, n_hi=1 << 19, seed=3)
     xs = []
     for w in wls:
@@ -125,12 +128,24 @@ def test_dm_trial_batch_sampled_parity(ctx, pk, oracle_lib):
         xs.append(x)
     ds = [to_device(x) for x in xs]
     zs = [w.zmax for w in wls]
-    got, n, used = ctx.pulscan_search_batched(ds, zs, 1024, 6.0)
-    assert n == len(got) and used == 1024
+    got, n, used = ctx.pulscan_search_batched(ds, zs, chunk, 6.0)
+    assert n == len(got) and used == chunk
     keys = [(int(c["spectrum"]), int(c["chunk"]), int(c["width"])) for c in got]
     assert keys == sorted(keys)
     for s in (0, 17, 63):
-        orc = oracle_lib.search(xs[s], zs[s], 1024, 6.0, tables=True)
+        orc = oracle_lib.search(xs[s], zs[s], chunk, 6.0, tables=True)
         nt = float(xs[s].shape[0] * zs[s])
         compare_candidates(got[got["spectrum"] == s], orc, orc.P, nt, 6.0, oracle_lib,
                            label=f"batch spectrum {s}")
+
+
+def test_plain_search_with_many_tiles(ctx, pk, oracle_lib):
+    """2^21 bins in 64-bin chunks: over 8000 tiles, scanned in two levels."""
+    wl = synth.workload("plain_2e23")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=1 << 21)
+    got, n = ctx.pulscan_search_ex(to_device(x), 200, 64, 6.0)
+    assert n == len(got) > 0
+    orc = oracle_lib.search(x, 200, 64, 6.0, tables=True)
+    compare_candidates(got, orc, orc.P, float(len(x) * 200), 6.0, oracle_lib, "many tiles")
+    again, n2 = ctx.pulscan_search_ex(to_device(x), 200, 64, 6.0)
+    assert n2 == n and (again == got).all()

@@ -1,0 +1,47 @@
+"""The serving runtime's host logic on the CPU: its source compiled against
+host stand-ins for HIP and for the search (tests/serve_stub), driven through
+admission with small and large device budgets, one or many spectra per
+launch, host and device spectra, and a ring that wraps."""
+
+import os
+import shutil
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+STUB = os.path.join(ROOT, "tests", "serve_stub")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not installed")
+    d = tmp_path_factory.mktemp("serve")
+    out = d / "drive"
+    # the runtime's source next to the stand-in header, so that its
+    # #include "internal.hpp" resolves to the stand-in
+    shutil.copy(os.path.join(ROOT, "paper_2406_15186_amd", "csrc", "serve.hip"), d / "serve.cpp")
+    shutil.copy(os.path.join(STUB, "internal.hpp"), d / "internal.hpp")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-pthread", "-I", os.path.join(ROOT, "include"),
+           str(d / "serve.cpp"), os.path.join(STUB, "stub_search.cpp"),
+           os.path.join(STUB, "drive.cpp"), "-o", str(out)]
+    subprocess.run(cmd, check=True)
+    return str(out)
+
+
+# spectra are drawn up to the whole budget in size (about two fit on
+# average), so admission waits for room and the ring wraps constantly
+@pytest.mark.parametrize("budget,max_batch,nreq,seed", [
+    (1 << 20, 256, 50, 1),     # many spectra per launch
+    (1 << 20, 1, 50, 2),       # one spectrum per launch
+    (1 << 20, 3, 300, 3),
+    (1 << 21, 1, 300, 4),
+    (1 << 21, 7, 400, 5),
+])
+def test_every_request_completes_once(driver, budget, max_batch, nreq, seed):
+    r = subprocess.run([driver, str(budget), str(max_batch), str(nreq), str(seed)],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert r.stdout.startswith(f"ok {nreq}")
