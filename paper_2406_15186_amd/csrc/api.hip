@@ -74,17 +74,14 @@ struct pulscan_ctx {
 
 namespace {
 
-// Device-resident counters of a search; zeroed when allocated.  The bank
-// kernel's last workgroup re-arms the pool head and the finished-tile count
-// at the end of every search.
+// Device-resident counters of a search; zeroed when allocated.  The scan of
+// the tile counts re-arms the pool head at the end of every search.
 struct Counters {
   unsigned long long total;
+  unsigned long long best;   // candidates kept by the final pass (best / re-check)
+  uint32_t head;             // next free staging-pool entry
   uint32_t overflow;
-  uint32_t head;
-  uint32_t done;
-  uint32_t gen;             // generation tag of the last launch's tile words
-  unsigned long long best;  // candidates kept by the final pass (best / re-check)
-  uint32_t lost;            // two-level scan: a tile's count was missing
+  uint32_t lost;             // two-level scan: a tile's count was missing
   uint32_t pad;
 };
 
@@ -394,9 +391,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     bp.pool = static_cast<StageEntry *>(ctx->pool.p);
     bp.pool_cap = pool_cap;
     bp.pool_head = &cnt->head;
-    bp.done = &cnt->done;
     bp.tile_word = static_cast<unsigned long long *>(ctx->tile_word.p);
-    bp.gen = &cnt->gen;
     bp.tile_prefix = static_cast<uint32_t *>(ctx->tile_prefix.p);
     bp.total = &cnt->total;
     bp.total2 = fin ? nullptr : reinterpret_cast<unsigned long long *>(a.out->count_device);
@@ -448,9 +443,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     bs.span_sum = static_cast<uint32_t *>(ctx->span_sum.p);
     bs.span_prefix = static_cast<uint32_t *>(ctx->span_prefix.p);
     bs.total_tiles = tiles;
-    bs.gen = bp.gen;
     bs.pool_head = bp.pool_head;
-    bs.done = bp.done;
     bs.pool_cap = pool_cap;
     bs.total = bp.total;
     bs.total2 = bp.total2;

@@ -589,41 +589,40 @@ __device__ __forceinline__ void eval_unit(const PT *__restrict__ Pl,
   width_block<K>(q, hb, t, k0, Tl + b * K, b * K, zmax, slot_row, bin0);
 }
 
-// Exclusive scan of the per-tile candidate counts by the workgroup that
-// started last.  Each tile publishes its count as one relaxed 64-bit word
-// (generation << 32 | count); a word of an earlier launch is waited for
-// rather than fenced, so no tile pays for a device-wide release.  The
-// generation lives in device memory: every tile reads it when it starts and
-// the scanning tile advances it after every tile has published, so launches
-// replayed from a graph still tag their words apart.  Thread t
-// sums a contiguous run of tiles, the run totals are scanned across the
-// workgroup, and each thread writes its run's prefixes.  Also records the
-// total and the staging overflow, and re-arms the pool head and the
-// finished-tile counter for the next launch.
+// Exclusive scan of the per-tile candidate counts by the workgroup of the
+// last index, after its own tile (it is dispatched last, so its polls overlap
+// the tiles still running; it holds one slot, so every other workgroup can
+// still be dispatched while it waits).  Each tile publishes its count as one relaxed 64-bit word
+// (kTilePublished | count); a word not yet published is waited for rather
+// than fenced, so no tile pays for a device-wide release.  The scan clears
+// every word it reads, so the next launch (or graph replay) starts from
+// unpublished words without any per-launch tag.  Thread t sums a contiguous
+// run of tiles, the run totals are scanned across the workgroup, and each
+// thread writes its run's prefixes.  Also records the total and the staging
+// overflow, and re-arms the pool head for the next launch.
 constexpr uint32_t kWordSpin = 1u << 22;  // polls per word before giving up
 
-__device__ __forceinline__ uint32_t tile_count_of(const BankParams &p, uint64_t i, uint32_t gen,
-                                                  bool &lost) {
+__device__ __forceinline__ uint32_t tile_count_of(const BankParams &p, uint64_t i, bool &lost) {
   unsigned long long v = 0;
   for (uint32_t k = 0; k < kWordSpin; ++k) {
     v = __hip_atomic_load(p.tile_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((uint32_t)(v >> 32) == gen) return (uint32_t)v;
+    if (v & kTilePublished) return (uint32_t)v;
     __builtin_amdgcn_s_sleep(1);
   }
   lost = true;  // reported through the overflow flag
   return 0u;
 }
 
-__device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uint32_t gen,
-                           uint32_t *wave_sum, uint32_t *lost_any) {
+__device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uint32_t *wave_sum,
+                           uint32_t *lost_any) {
   const uint32_t lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
   const uint64_t T = p.total_tiles;
   const uint64_t per = (T + nthr - 1) / nthr;
   const uint64_t lo = min((uint64_t)tid * per, T), hi = min(lo + per, T);
   bool lost = false;
   uint32_t mine = 0;
-  // eight independent loads in flight; a word not yet tagged with this
-  // launch's generation is then waited for on its own
+  // eight independent loads in flight; a word not yet published is then
+  // waited for on its own
   uint64_t i = lo;
   for (; i + 8 <= hi; i += 8) {
     unsigned long long v[8];
@@ -632,9 +631,9 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
       v[k] = __hip_atomic_load(p.tile_word + i + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      mine += (uint32_t)(v[k] >> 32) == gen ? (uint32_t)v[k] : tile_count_of(p, i + k, gen, lost);
+      mine += (v[k] & kTilePublished) ? (uint32_t)v[k] : tile_count_of(p, i + k, lost);
   }
-  for (; i < hi; ++i) mine += tile_count_of(p, i, gen, lost);
+  for (; i < hi; ++i) mine += tile_count_of(p, i, lost);
   if (lost) atomicOr(lost_any, 1u);
   uint32_t incl = mine;
 #pragma unroll
@@ -653,6 +652,7 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
   for (uint64_t j = lo; j < hi; ++j) {
     p.tile_prefix[j] = run;
     run += (uint32_t)__hip_atomic_load(p.tile_word + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p.tile_word + j, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (tid == 0) {
@@ -661,8 +661,6 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
     if (p.total2) *p.total2 = tot;
     *p.overflow = *lost_any ? 2u : (tot > p.pool_cap ? 1u : 0u);
     __hip_atomic_store(p.pool_head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p.gen, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -688,7 +686,6 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
   __shared__ uint32_t n_items;
   __shared__ uint32_t is_last;
   __shared__ uint32_t lost_any;
-  __shared__ uint32_t launch_gen;
   constexpr uint32_t SEG = 64 * K;
   constexpr uint32_t B = 64 * EPL;
   constexpr int PITCH = pitch_of<K>();
@@ -716,8 +713,6 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
   if (first_tile >= p.total_tiles) return;
   {
     const uint64_t tg = first_tile;
-    uint32_t ticket = 0;  // thread 0: this tile's place in the order tiles start
-    uint32_t gen = 0;     // thread 0: this launch's generation tag
     int sidx = 0;
     if (p.nspec > 1) {
       int lo = 0, hi = p.nspec - 1;
@@ -751,14 +746,6 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
     if (tid == 0) {
       any_dense = 0u;
       n_items = 0u;
-      // the tile that starts last scans the per-tile counts once every tile
-      // has published its count; taking the ticket now hides its latency
-      // behind the spectrum loads
-      if (p.mode == kModeSearch) {
-        if (p.scan_in_kernel) ticket = atomicAdd(p.done, 1u);
-        gen = __hip_atomic_load(p.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-        if (gen == 0u) gen = 1u;  // words start at generation 0
-      }
     }
     if (!power_only) {
     for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
@@ -906,12 +893,12 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
       if (tid == 0) {
         tile_base = tot ? atomicAdd(p.pool_head, tot) : 0u;
         // the pool reservation has been performed before the count is
-        // published, so the scanning tile may re-arm the pool head
+        // published, so the scan (which waits for every count) may re-arm
+        // the pool head
         __builtin_amdgcn_s_waitcnt(0);
-        __hip_atomic_store(p.tile_word + tg, ((unsigned long long)gen << 32) | tot,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = p.scan_in_kernel && ticket == (uint32_t)(p.total_tiles - 1) ? 1u : 0u;
-        launch_gen = gen;
+        __hip_atomic_store(p.tile_word + tg, kTilePublished | tot, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        is_last = p.scan_in_kernel && blockIdx.x == gridDim.x - 1 ? 1u : 0u;
         lost_any = 0u;
       }
       __syncthreads();
@@ -931,8 +918,8 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
         }
         ++rank;
       }
-      // the last tile to finish scans the per-tile counts
-      if (is_last) scan_tiles(p, tid, nthr, launch_gen, wave_sum, &lost_any);
+      // the workgroup of the last index scans the per-tile counts
+      if (is_last) scan_tiles(p, tid, nthr, wave_sum, &lost_any);
     } else {
       for (uint32_t i = tid; i < nsl; i += nthr) {
         const unsigned long long key = slots[i];
@@ -1098,8 +1085,6 @@ constexpr int kBigThreads = 512;
 __global__ __launch_bounds__(kBigThreads) void scan_span_kernel(BigScan s) {
   __shared__ uint32_t wave_sum[kBigThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t gen = __hip_atomic_load(s.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-  const uint32_t want = gen ? gen : 1u;
   const uint64_t base = (uint64_t)blockIdx.x * kScanSpan;
   constexpr uint32_t PER = kScanSpan / kBigThreads;
   uint32_t v[PER];
@@ -1110,8 +1095,9 @@ __global__ __launch_bounds__(kBigThreads) void scan_span_kernel(BigScan s) {
     uint32_t c = 0;
     if (i < s.total_tiles) {
       const unsigned long long w = s.tile_word[i];  // written by the previous kernel
-      c = (uint32_t)(w >> 32) == want ? (uint32_t)w : 0u;
-      if ((uint32_t)(w >> 32) != want) atomicOr(s.lost, 1u);
+      c = (uint32_t)w;
+      if (!(w & kTilePublished)) atomicOr(s.lost, 1u);
+      s.tile_word[i] = 0ull;
     }
     v[k] = c;
     mine += c;
@@ -1168,10 +1154,7 @@ __global__ __launch_bounds__(kBigThreads) void scan_top_kernel(BigScan s, uint32
     if (s.total2) *s.total2 = carry;
     *s.overflow = *s.lost ? 2u : (carry > s.pool_cap ? 1u : 0u);
     *s.lost = 0u;
-    const uint32_t g = *s.gen + 1u;
-    *s.gen = g ? g : 1u;
     *s.pool_head = 0u;
-    *s.done = 0u;
   }
 }
 

@@ -72,13 +72,12 @@ struct BankParams {
   int dense;               // 1: skip the pruning bound (every width block evaluated)
   int norm_exact;          // 1: exact median / MAD instead of the median of medians
   // search mode: candidate staging and the scan of the per-tile counts,
-  // which the workgroup that finishes last performs
+  // which the workgroup of the last index performs after its own tile
   StageEntry *pool;        // staging pool
   uint32_t pool_cap;       // entries in the pool
   uint32_t *pool_head;     // next free pool entry (re-armed to 0 by the scan)
-  uint32_t *done;          // tiles finished (re-armed to 0 by the scan)
-  unsigned long long *tile_word;  // per tile: gen << 32 | candidates it staged
-  uint32_t *gen;           // generation of the last launch (device; words start at 0)
+  unsigned long long *tile_word;  // per tile: kTilePublished | candidates it staged
+                                  // (0 until published; the scan clears it)
   uint32_t *tile_prefix;   // per tile: exclusive prefix of the counts; [total_tiles] = total
   unsigned long long *total;   // candidate count (device)
   unsigned long long *total2;  // optional second destination (the caller's)
@@ -89,6 +88,9 @@ struct BankParams {
   float *P_out;            // tables mode, optional: normalised power
   float *stats_out;        // tables mode, optional: 4 floats per block
 };
+
+// A tile word holds this flag once the tile has published its count.
+constexpr unsigned long long kTilePublished = 1ull << 32;
 
 // Chosen launch geometry of a search.
 struct Geometry {
@@ -137,18 +139,16 @@ hipError_t launch_thresholds(const ThreshJob *jobs_dev, const ThreshJob &single,
 // two kernels after the bank kernel: each workgroup scans kScanSpan tiles
 // into tile_prefix (relative to its span) and writes the span's total; one
 // workgroup scans the span totals into span_prefix, records the total and
-// the overflow flag, and re-arms the pool head, the finished-tile counter
-// and the generation.
+// the overflow flag, and re-arms the pool head.  The span scan clears the
+// tile words it reads.
 constexpr uint32_t kScanSpan = 4096;
 struct BigScan {
-  const unsigned long long *tile_word;
+  unsigned long long *tile_word;
   uint32_t *tile_prefix;
   uint32_t *span_sum;
   uint32_t *span_prefix;
   uint64_t total_tiles;
-  uint32_t *gen;                   // the bank launch's generation is *gen + 1
   uint32_t *pool_head;
-  uint32_t *done;
   uint32_t pool_cap;
   unsigned long long *total;
   unsigned long long *total2;
