@@ -621,9 +621,25 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
   const uint64_t lo = min((uint64_t)tid * per, T), hi = min(lo + per, T);
   bool lost = false;
   uint32_t mine = 0;
-  // eight independent loads in flight; a word not yet published is then
-  // waited for on its own
-  uint64_t i = lo;
+  // the run's first R counts stay in registers; eight independent loads are
+  // in flight at a time, and a word not yet published is then waited for on
+  // its own
+  constexpr int R = 8;
+  uint32_t first[R];
+  {
+    unsigned long long v[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      v[k] = lo + k < hi ? __hip_atomic_load(p.tile_word + lo + k, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                         : kTilePublished;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      first[k] = (v[k] & kTilePublished) ? (uint32_t)v[k] : tile_count_of(p, lo + k, lost);
+      mine += first[k];
+    }
+  }
+  uint64_t i = lo + R;
   for (; i + 8 <= hi; i += 8) {
     unsigned long long v[8];
 #pragma unroll
@@ -649,7 +665,15 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
     tot += wave_sum[v];
   }
   run += incl - mine;
-  for (uint64_t j = lo; j < hi; ++j) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (lo + k < hi) {
+      p.tile_prefix[lo + k] = run;
+      run += first[k];
+      __hip_atomic_store(p.tile_word + lo + k, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  for (uint64_t j = lo + R; j < hi; ++j) {
     p.tile_prefix[j] = run;
     run += (uint32_t)__hip_atomic_load(p.tile_word + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(p.tile_word + j, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -829,23 +853,28 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
       }
       }
       __syncthreads();
-      // work units (flagged lane, width block), lane-major, so that the lanes
-      // of a wave share lanes' chunks but not widths: their slot merges
-      // rarely collide
+      // work units (flagged lane, width block, half of the lane's starts).
+      // The (lane, block) pairs are lane-major, so that the lanes of a wave
+      // share lanes' chunks but not widths and their slot merges rarely
+      // collide; every 64 pairs are taken once per half by whole waves, so
+      // that a wave runs one half's code only.
       const uint32_t tid = fresh_tid();
       const uint32_t nb = (zmax + K - 1) / K;
       constexpr uint32_t NH = K / ks_of<K>();  // start groups per lane
-      const uint32_t nunits = n_items * nb * NH;
-      if (tid == 0 && nunits) any_dense = 1u;
-      for (uint32_t r = 0; r < nunits; r += nthr) {
+      const uint32_t npairs = n_items * nb;
+      const uint32_t nrun = (npairs + 63) / 64 * 64 * NH;
+      if (tid == 0 && npairs) any_dense = 1u;
+      for (uint32_t r = 0; r < nrun; r += nthr) {
         const uint32_t j = r + tid;
-        const uint32_t jj = j / NH;
-        const uint32_t it = j < nunits ? items[jj / nb] : 0u;
-        const uint32_t b = j < nunits ? jj % nb : 0u;
-        if (j < nunits && b >= (it & 0xFFFu)) {
+        const uint32_t grp = j >> 6, half = grp % NH;
+        const uint32_t u = (grp / NH) * 64 + (j & 63);
+        const bool ok = j < nrun && u < npairs;
+        const uint32_t it = ok ? items[u / nb] : 0u;
+        const uint32_t b = ok ? u % nb : 0u;
+        if (ok && b >= (it & 0xFFFu)) {
           const uint32_t L = it >> 12;
           unsigned long long *row = slots + (size_t)((L * K) / C) * zmax;
-          if (NH == 1 || j % NH == 0)
+          if (NH == 1 || half == 0)
             eval_unit<K, PT>(Pl, Sg, Tl, L, b, 0, rem, zmax, row, t0 + L * K);
           else
             eval_unit<K, PT>(Pl, Sg, Tl, L, b, ks_of<K>(), rem, zmax, row, t0 + L * K);
