@@ -189,7 +189,9 @@ def serving_leg(pk, synth, args, tone_power):
         hosts.append(hp)
         torch.cuda.synchronize()
         import ctypes
-        ctypes.memmove(hp, x.cpu().numpy().ctypes.data, n * 8)
+        xh = x.cpu().numpy()  # held while copied: .ctypes.data alone keeps no reference
+        ctypes.memmove(hp, xh.ctypes.data, n * 8)
+        del xh
         host_pool.append((hp, n, 200))
     dev_pool = [(x.data_ptr(), n, z) for x, n, z in pool]
     out = {}
