@@ -35,6 +35,30 @@
 
 namespace pulscan {
 
+// Global-memory view of a pointer the kernels receive inside a structure.
+// The compiler cannot infer the address space of such pointers, and generic
+// (flat) accesses are also counted against the LDS wait counter, so every LDS
+// wait would wait for outstanding spectrum loads too.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL_AS T *glob(T *p) {
+  return (GLOBAL_AS T *)p;
+}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// A series descriptor read from the device table as 64-bit words.
+__device__ __forceinline__ SpecDesc load_desc(const SpecDesc *p) {
+  static_assert(sizeof(SpecDesc) % 8 == 0, "descriptor of whole words");
+  constexpr int W = sizeof(SpecDesc) / 8;
+  const GLOBAL_AS unsigned long long *g = glob(reinterpret_cast<const unsigned long long *>(p));
+  unsigned long long w[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) w[k] = g[k];
+  SpecDesc d;
+  __builtin_memcpy(&d, w, sizeof d);
+  return d;
+}
+
 // Row pitch (floats) of the power tile for K bins per lane: the 64 lane
 // columns plus 64/K pad words, so that the bank's reads (64 consecutive
 // words of a row) and the normalisation's writes (lane l -> row l % K,
@@ -44,12 +68,26 @@ __host__ __device__ constexpr int pitch_of() {
   return K == 1 ? 64 : 64 + 64 / K;
 }
 
-// Twice the median of four values: the two middle values of four are
-// max(min(a,b), min(c,d)) and min(max(a,b), max(c,d)).  Carrying the factor
-// 2 through the tree and removing it with one exact power-of-two scale at the
-// end rounds exactly as halving at every level would.
+// Twice the median of four values, i.e. the sum of the middle two.  With m
+// the median of a, b, c and lo, hi their minimum and maximum, adding d
+// leaves {m, median(lo, d, hi)} as the middle pair, so the result is one
+// rounding of the sum of the same two values however they are picked.
+// Carrying the factor 2 through the tree and removing it with one exact
+// power-of-two scale at the end rounds exactly as halving at every level
+// would.  Inputs are finite.
 __device__ __forceinline__ float m4x2(float a, float b, float c, float d) {
-  return fmaxf(fminf(a, b), fminf(c, d)) + fminf(fmaxf(a, b), fmaxf(c, d));
+  const float m = __builtin_amdgcn_fmed3f(a, b, c);
+  const float lo = fminf(fminf(a, b), c), hi = fmaxf(fmaxf(a, b), c);
+  return m + __builtin_amdgcn_fmed3f(lo, d, hi);
+}
+// The same for values just loaded from memory: min and max as medians with
+// an infinite third operand, which the compiler does not precede with a
+// quieting of signalling NaNs as it does for fminf / fmaxf of loaded values.
+__device__ __forceinline__ float m4x2_ld(float a, float b, float c, float d) {
+  const float m = __builtin_amdgcn_fmed3f(a, b, c);
+  const float lo = __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, b, -INFINITY), c, -INFINITY);
+  const float hi = __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, b, INFINITY), c, INFINITY);
+  return m + __builtin_amdgcn_fmed3f(lo, d, hi);
 }
 
 template <int CTRL>
@@ -87,8 +125,13 @@ __device__ __forceinline__ void wave_mom2(float (&a)[EPL], float (&b)[EPL], floa
     const int q = cnt / 4;
 #pragma unroll
     for (int m = 0; m < q; ++m) {
-      a[m] = m4x2(a[m], a[m + q], a[m + 2 * q], a[m + 3 * q]);
-      b[m] = m4x2(b[m], b[m + q], b[m + 2 * q], b[m + 3 * q]);
+      if (cnt == EPL) {  // the inputs themselves (or their deviations)
+        a[m] = m4x2_ld(a[m], a[m + q], a[m + 2 * q], a[m + 3 * q]);
+        b[m] = m4x2_ld(b[m], b[m + q], b[m + 2 * q], b[m + 3 * q]);
+      } else {
+        a[m] = m4x2(a[m], a[m + q], a[m + 2 * q], a[m + 3 * q]);
+        b[m] = m4x2(b[m], b[m + q], b[m + 2 * q], b[m + 3 * q]);
+      }
     }
   }
   float x = a[0], y = b[0];
@@ -123,7 +166,7 @@ __device__ __forceinline__ float wave_mom1(const float (&a)[EPL], float c) {
     float e[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) e[j] = DEV ? fabsf(a[m + j * Q] - c) : a[m + j * Q];
-    v[m] = m4x2(e[0], e[1], e[2], e[3]);
+    v[m] = DEV ? m4x2(e[0], e[1], e[2], e[3]) : m4x2_ld(e[0], e[1], e[2], e[3]);
   }
 #pragma unroll
   for (int cnt = Q; cnt >= 4; cnt /= 4) {
@@ -278,7 +321,7 @@ __device__ __forceinline__ void load_block(const float2 *__restrict__ x, uint32_
   bd.s0 = bd.last ? n - B : bd.own;
 #pragma unroll
   for (int m = 0; m < EPL; ++m) {
-    const float2 v = x[bd.s0 + lane + 64 * m];
+    const f32x2 v = glob(reinterpret_cast<const f32x2 *>(x))[bd.s0 + lane + 64 * m];
     bd.re[m] = v.x;
     bd.im[m] = v.y;
   }
@@ -346,15 +389,16 @@ __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, 
         const float c = fmaf(im[m], inv_im, off_im);
         const float P = fmaf(a, a, c * c);
         Pl[paddr<K>(t - t0)] = to_pt<PT>(P);
-        if (P_out && t - t0 < T) P_out[t] = P;
+        if (P_out && t - t0 < T) glob(P_out)[t] = P;
       }
     }
   }
   if (stats_out && lane == 0 && own >= t0 && own < t0 + T) {
-    stats_out[4 * (size_t)b + 0] = med_re;
-    stats_out[4 * (size_t)b + 1] = mad_re;
-    stats_out[4 * (size_t)b + 2] = med_im;
-    stats_out[4 * (size_t)b + 3] = mad_im;
+    GLOBAL_AS float *st = glob(stats_out) + 4 * (size_t)b;
+    st[0] = med_re;
+    st[1] = mad_re;
+    st[2] = med_im;
+    st[3] = mad_im;
   }
 }
 
@@ -491,6 +535,13 @@ __device__ __forceinline__ void bank_dense(const PT *__restrict__ Pl, uint32_t g
 // the ratio of the two stays above 1 - 2^-10, so comparing a union sum with
 // T * (1 - 2^-10) never skips a window whose FP32 boxcar reaches T.
 constexpr float kBoundSlack = 1.0f - 1.0f / 1024.0f;
+// max(v, 0) of a power read from the tile (-inf past the spectrum's end),
+// without the quieting of signalling NaNs that fmaxf of a loaded value gets
+__device__ __forceinline__ float clamp0(float v) {
+  return __builtin_amdgcn_fmed3f(v, 0.f, INFINITY);
+}
+
+constexpr int kBoundBatch = 8;  // width blocks per step of the bound's later blocks
 constexpr int kSub = 4;  // widths per bound check inside the first width block
 
 // The first width block in which one of this lane's windows might reach its
@@ -511,26 +562,45 @@ __device__ __forceinline__ uint32_t bound_lane(const PT *__restrict__ Pl,
   const PT *bp = Pl + g * (K * PITCH) + lane;
   const uint32_t L1 = lane + 1;
   const PT *bq = Pl + (g + (L1 >> 6)) * (K * PITCH) + (L1 & 63);
+  // every load is issued before the sums use them
+  float v[2 * K - 1];
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = (float)bp[j * PITCH];
+#pragma unroll
+  for (int u = 1; u < K; ++u) v[K - 1 + u] = (float)bq[(u - 1) * PITCH];
+  float t1[(K + S - 1) / S];
+#pragma unroll
+  for (int i = 0; i < (K + S - 1) / S; ++i) t1[i] = Tb1[i];
   float U = 0.f;
 #pragma unroll
-  for (int j = 0; j < K - 1; ++j) {
-    const float v = (float)bp[j * PITCH];
-    U += CLAMP ? fmaxf(v, 0.f) : v;
-  }
+  for (int j = 0; j < K - 1; ++j) U += CLAMP ? clamp0(v[j]) : v[j];
   bool hit = false;
 #pragma unroll
   for (int u = 0; u < K; ++u) {
-    const float v = u == 0 ? (float)bp[(K - 1) * PITCH] : (float)bq[(u - 1) * PITCH];
-    U += CLAMP ? fmaxf(v, 0.f) : v;
-    if ((u + 1) % S == 0) hit = hit || (U >= Tb1[u / S]);
+    U += CLAMP ? clamp0(v[K - 1 + u]) : v[K - 1 + u];
+    if ((u + 1) % S == 0) hit |= U >= t1[u / S];
   }
   uint32_t fl = hit ? 0u : nblk;
   const uint32_t own = g * 64 + lane;
   U = Sg[own] + Sg[own + 1];
-  for (uint32_t b = 1; b < nblk; ++b) {
+  // blocks are taken kBoundBatch at a time with their loads issued together
+  // (indices clamped to the last block, whose terms are then not used)
+  for (uint32_t b = 1; b < nblk; b += kBoundBatch) {
     if (__ballot(fl == nblk) == 0ull) break;  // every lane already flagged
-    U += Sg[own + b + 1];
-    if (fl == nblk && U >= Tb[b]) fl = b;
+    float sg[kBoundBatch], tb[kBoundBatch];
+#pragma unroll
+    for (int k = 0; k < kBoundBatch; ++k) {
+      const uint32_t bb = min(b + k, nblk - 1);
+      sg[k] = Sg[own + bb + 1];
+      tb[k] = Tb[bb];
+    }
+#pragma unroll
+    for (int k = 0; k < kBoundBatch; ++k) {
+      if (b + k < nblk) {
+        U += sg[k];
+        if (fl == nblk && U >= tb[k]) fl = b + k;
+      }
+    }
   }
   return fl;
 }
@@ -694,7 +764,7 @@ constexpr int threads_for() {
 }
 // Waves per SIMD the register allocation must allow: 6 lets three 8-wave
 // workgroups share a CU.  The exact median keeps a block's keys in
-// registers and settles for two.
+// registers and settles for four.
 template <int EPL, bool EXACT>
 constexpr int waves_per_eu_for() {
   return EPL >= 64 ? 1 : EXACT ? 4 : 6;
@@ -708,7 +778,6 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
   __shared__ uint32_t tile_base;
   __shared__ uint32_t any_dense;
   __shared__ uint32_t n_items;
-  __shared__ uint32_t is_last;
   __shared__ uint32_t lost_any;
   constexpr uint32_t SEG = 64 * K;
   constexpr uint32_t B = 64 * EPL;
@@ -742,14 +811,14 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
       int lo = 0, hi = p.nspec - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (p.descs[mid].tile_begin <= tg)
+        if (glob(p.descs)[mid].tile_begin <= tg)
           lo = mid;
         else
           hi = mid - 1;
       }
       sidx = lo;
     }
-    const SpecDesc d = p.nspec > 1 ? p.descs[sidx] : p.single;
+    const SpecDesc d = p.nspec > 1 ? load_desc(p.descs + sidx) : p.single;
     const uint32_t t0 = (uint32_t)(tg - d.tile_begin) * T;
     const uint32_t n = d.n, zmax = d.zmax, zc = d.zc;
     const uint32_t rem = n - t0;
@@ -772,18 +841,21 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
       n_items = 0u;
     }
     if (!power_only) {
-    for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
-    for (uint32_t i = tid; i < zc; i += nthr) Tl[i] = d.thr[i];
+    // the pruned search clears the slots only once it has work items
+    if (p.dense || p.mode == kModeTables)
+      for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
+    const GLOBAL_AS float *gthr = glob(d.thr);
+    for (uint32_t i = tid; i < zc; i += nthr) Tl[i] = gthr[i];
     if (tid < 4) {
       constexpr int S = K < kSub ? K : kSub;
       float m = INFINITY;
       if (tid * S < (uint32_t)K)
-        for (int u = 0; u < S; ++u) m = fminf(m, d.thr[tid * S + u]);
+        for (int u = 0; u < S; ++u) m = fminf(m, gthr[tid * S + u]);
       Tb1[tid] = m * kBoundSlack;
     }
     for (uint32_t i = tid; i < nblk; i += nthr) {
-      float m = d.thr[i * K];
-      for (int u = 1; u < K; ++u) m = fminf(m, d.thr[i * K + u]);
+      float m = gthr[i * K];
+      for (int u = 1; u < K; ++u) m = fminf(m, gthr[i * K + u]);
       Tb[i] = m * kBoundSlack;
     }
     }
@@ -794,7 +866,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
       Pl[paddr<K>(i)] = to_pt<PT>(i < rem ? 0.f : -INFINITY);
     if (p.from_power) {
       const float *pw = reinterpret_cast<const float *>(d.x);
-      for (uint32_t i = tid; i < need; i += nthr) Pl[paddr<K>(i)] = to_pt<PT>(pw[t0 + i]);
+      for (uint32_t i = tid; i < need; i += nthr) Pl[paddr<K>(i)] = to_pt<PT>(glob(pw)[t0 + i]);
     } else if (have) {
       const bool dbg = p.mode == kModeTables;
       float *po = power_only ? d.aux : dbg ? p.P_out : nullptr;
@@ -822,7 +894,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
         float a = 0.f;
         if (clamp) {
 #pragma unroll
-          for (int v = 0; v < K; ++v) a += fmaxf((float)cp[v * PITCH], 0.f);
+          for (int v = 0; v < K; ++v) a += clamp0((float)cp[v * PITCH]);
         } else {
 #pragma unroll
           for (int v = 0; v < K; ++v) a += (float)cp[v * PITCH];
@@ -853,6 +925,11 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
       }
       }
       __syncthreads();
+      if (n_items) {
+        const uint32_t tid = fresh_tid();
+        for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
+        __syncthreads();
+      }
       // work units (flagged lane, width block, half of the lane's starts).
       // The (lane, block) pairs are lane-major, so that the lanes of a wave
       // share lanes' chunks but not widths and their slot merges rarely
@@ -898,11 +975,24 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
     const uint32_t chunk0 = t0 / C;
     const uint32_t nch = min(chunks_per_tile, d.nchunks - chunk0);
     const uint32_t nsl = nch * zmax;
-    if (p.mode == kModeSearch) {
+    // the workgroup of the last index scans the per-tile counts
+    const bool scanner = p.scan_in_kernel && blockIdx.x == gridDim.x - 1;
+    if (p.mode == kModeSearch && !any_dense) {
+      // nothing was evaluated, so nothing reached a threshold
+      if (tid == 0) {
+        __hip_atomic_store(p.tile_word + tg, kTilePublished, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        lost_any = 0u;
+      }
+      if (scanner) {
+        __syncthreads();
+        scan_tiles(p, tid, nthr, wave_sum, &lost_any);
+      }
+    } else if (p.mode == kModeSearch) {
       // stage the tile's maxima in slot order, i.e. (chunk, width) order:
       // thread t takes a contiguous run of slots; ranks come from a scan of
       // the run counts, one atomic reserves the tile's run of the pool
-      const uint32_t per = any_dense ? (nsl + nthr - 1) / nthr : 0u;
+      const uint32_t per = (nsl + nthr - 1) / nthr;
       const uint32_t lo = min(tid * per, nsl), hi = min(lo + per, nsl);
       uint32_t mine = 0;
       for (uint32_t i = lo; i < hi; ++i) mine += slots[i] != 0ull ? 1u : 0u;
@@ -927,7 +1017,6 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
         __builtin_amdgcn_s_waitcnt(0);
         __hip_atomic_store(p.tile_word + tg, kTilePublished | tot, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        is_last = p.scan_in_kernel && blockIdx.x == gridDim.x - 1 ? 1u : 0u;
         lost_any = 0u;
       }
       __syncthreads();
@@ -947,8 +1036,7 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
         }
         ++rank;
       }
-      // the workgroup of the last index scans the per-tile counts
-      if (is_last) scan_tiles(p, tid, nthr, wave_sum, &lost_any);
+      if (scanner) scan_tiles(p, tid, nthr, wave_sum, &lost_any);
     } else {
       for (uint32_t i = tid; i < nsl; i += nthr) {
         const unsigned long long key = slots[i];
