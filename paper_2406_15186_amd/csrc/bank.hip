@@ -90,9 +90,13 @@ __device__ __forceinline__ float m4x2_ld(float a, float b, float c, float d) {
   return m + __builtin_amdgcn_fmed3f(lo, d, hi);
 }
 
+// Lane l of each row of 16 receives lane l + k's value (row_shl k); lanes
+// whose source lies past the row's end read 0 (bound control), so no old
+// value has to be set up.  Only lanes whose sources lie inside the row are
+// used.
 template <int CTRL>
 __device__ __forceinline__ float dpp_row(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl3 = 0x103;
 constexpr int kRowShl4 = 0x104, kRowShl8 = 0x108, kRowShl12 = 0x10C;
