@@ -13,30 +13,74 @@ namespace pulscan {
 // log P(chi^2(2w) > x).  For even dof the survival function is
 // exp(-x/2) * sum_{k<w} (x/2)^k / k!; the sum is taken relative to its largest
 // term (at k = min(w-1, floor(x/2))) so that neither tail of it overflows.
+// log(k!) for an integer k: Stirling's series for k >= 16 (terms through
+// 1/x^7, error below 1e-16 relative there), a table below (the values of
+// log k! rounded to double).
+__device__ double log_factorial(uint32_t k) {
+  if (k < 16) {
+    constexpr double kSmall[16] = {
+        0.0, 0.0, 0.6931471805599453, 1.791759469228055, 3.1780538303479458, 4.787491742782046,
+        6.579251212010101, 8.525161361065415, 10.60460290274525, 12.801827480081469,
+        15.104412573075516, 17.502307845873887, 19.987214495661885, 22.552163853123425,
+        25.19122118273868, 27.89927138384089};
+    return kSmall[k];
+  }
+  const double x = (double)k + 1.0, ix = 1.0 / x, ix2 = ix * ix;
+  const double series =
+      ix * (1.0 / 12.0 - ix2 * (1.0 / 360.0 - ix2 * (1.0 / 1260.0 - ix2 * (1.0 / 1680.0))));
+  return (x - 0.5) * log(x) - x + 0.91893853320467274178 + series;
+}
+
 __device__ double log_sf_chi2_even(double x, uint32_t w) {
   if (!(x > 0.0)) return 0.0;
   const double y = 0.5 * x;
   const uint32_t kp = (y >= (double)(w - 1)) ? w - 1 : (uint32_t)floor(y);
-  const double log_peak = (double)kp * log(y) - lgamma((double)kp + 1.0);
+  const double log_peak = (double)kp * log(y) - log_factorial(kp);
+  // Terms are taken four at a time: the products of four ratios do not
+  // depend on the running term, so the dependent chain advances one
+  // multiplication per four terms (one candidate per thread, few threads:
+  // the chain's latency is the kernel's time).
   double acc = 1.0, r = 1.0;
   const double iy = 1.0 / y;
-  for (uint32_t k = kp; k >= 1; --k) {  // terms below the peak shrink by k / y
-    r *= (double)k * iy;
-    acc += r;
+  uint32_t k = kp;
+  for (; k >= 4; k -= 4) {  // terms below the peak shrink by k / y
+    const double a1 = (double)k * iy, a2 = (double)(k - 1) * iy;
+    const double a3 = (double)(k - 2) * iy, a4 = (double)(k - 3) * iy;
+    const double b12 = a1 * a2, b123 = b12 * a3, b1234 = b12 * (a3 * a4);
+    const double r1 = r * a1, r2 = r * b12, r3 = r * b123, r4 = r * b1234;
+    acc += (r1 + r2) + (r3 + r4);
+    r = r4;
     if (r < 1e-18 * acc) break;
   }
+  if (k < 4 && !(r < 1e-18 * acc)) {
+    for (; k >= 1; --k) {
+      r *= (double)k * iy;
+      acc += r;
+    }
+  }
   r = 1.0;
-  for (uint32_t k = kp + 1; k < w; ++k) {  // terms above the peak shrink by y / k
-    r *= y / (double)k;
-    acc += r;
+  k = kp + 1;
+  for (; k + 3 < w; k += 4) {  // terms above the peak shrink by y / k
+    const double a1 = y / (double)k, a2 = y / (double)(k + 1);
+    const double a3 = y / (double)(k + 2), a4 = y / (double)(k + 3);
+    const double b12 = a1 * a2, b123 = b12 * a3, b1234 = b12 * (a3 * a4);
+    const double r1 = r * a1, r2 = r * b12, r3 = r * b123, r4 = r * b1234;
+    acc += (r1 + r2) + (r3 + r4);
+    r = r4;
     if (r < 1e-18 * acc) break;
+  }
+  if (k + 3 >= w && !(r < 1e-18 * acc)) {
+    for (; k < w; ++k) {
+      r *= y / (double)k;
+      acc += r;
+    }
   }
   return -y + log_peak + log(acc);
 }
 
 // log of the chi^2(2w) density.
 __device__ double log_pdf_chi2_even(double x, uint32_t w) {
-  return (double)(w - 1) * log(0.5 * x) - 0.5 * x - M_LN2 - lgamma((double)w);
+  return (double)(w - 1) * log(0.5 * x) - 0.5 * x - M_LN2 - log_factorial(w - 1);
 }
 
 // log Phi_c(s), the standard normal upper tail.  For s > 0 the scaled
@@ -66,15 +110,25 @@ __device__ double sigma_from_logp(double L) {
   if (!(L < 0.0)) return -INFINITY;
   double s = 0.0;
   if (L < -1.0) {
+    // the tail's asymptotic form, log Q(s) ~ -s^2/2 - log(s sqrt(2 pi)) +
+    // log(1 - 1/s^2 + 3/s^4), solved by two fixed-point steps from the
+    // leading term, leaves Newton a few digits to add
     s = sqrt(-2.0 * L);
     s = sqrt(fmax(-2.0 * L - 2.0 * log(s * 2.5066282746310002), 1.0));
+    if (s > 2.0) {
+      const double q = 1.0 / (s * s);
+      s = sqrt(fmax(-2.0 * L - 2.0 * log(s * 2.5066282746310002) + 2.0 * log1p(q * (3.0 * q - 1.0)),
+                    1.0));
+    }
   }
+  // Newton on log Q; the result is reported in FP32, so a relative step of
+  // 1e-10 ends it
   for (int it = 0; it < 200; ++it) {
     double f, df;
     log_norm_sf_d(s, f, df);
     const double step = (f - L) / df;
     s -= step;
-    if (fabs(step) <= 1e-14 * fmax(1.0, fabs(s))) break;
+    if (fabs(step) <= 1e-10 * fmax(1.0, fabs(s))) break;
   }
   return s;
 }
@@ -162,6 +216,8 @@ __device__ float power32_window(const SpecDesc &d, uint32_t B, int from_power, u
 constexpr int kEmitThreads = 256;
 
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDesc single) {
+  // Each thread's significance is a long dependent chain: the entry's
+  // prefix is loaded before it and used only after it.
   const unsigned long long total = *p.total;
   const uint64_t lim = total < p.pool_cap ? total : p.pool_cap;
   const uint64_t stride = (uint64_t)gridDim.x * kEmitThreads;
@@ -169,7 +225,6 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
     const StageEntry e = p.pool[f];
     const uint64_t dest = (uint64_t)p.tile_prefix[e.tile] + (e.rank_width >> kWidthBits) +
                           (p.span_prefix ? p.span_prefix[e.tile / kScanSpan] : 0u);
-    if (dest >= p.capacity) continue;
     int s = 0;
     if (p.nspec > 1) {
       int a = 0, b = p.nspec - 1;
@@ -205,7 +260,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
     c.chunk = e.bin / p.chunk;
     c.harmonics = d.harm;
     c.reserved = 0u;
-    p.out[dest] = c;
+    if (dest < p.capacity) p.out[dest] = c;
   }
 }
 
