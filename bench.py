@@ -35,6 +35,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bank_kernel_plain_2e23_traffic.js
 BANK_SOURCE = os.path.join(ROOT, "paper_2406_15186_amd", "csrc", "bank.hip")
 
 
+TIMING_EVERY = 4  # bank launches per timed one
+
+
 def measured_traffic():
     """HBM bytes per bank-kernel launch from the committed counter summary, or
     None when there is none or the kernel source has changed since it was taken."""
@@ -278,7 +281,10 @@ def main():
     log(f"bench: warmup {args.warmup} done; timing {args.steps} steps")
 
     ctx.pulscan_ctx_kernel_time()
-    ctx.pulscan_ctx_set_timing(True)
+    # HIP events around every fourth bank launch of the timed steps: their
+    # average is the kernel's duration, and three steps in four carry no
+    # event overhead
+    ctx.pulscan_ctx_set_timing(TIMING_EVERY)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()

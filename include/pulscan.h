@@ -227,10 +227,13 @@ int pulscan_debug_bank_from_power(pulscan_ctx *ctx, const float *power, size_t n
 int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, double ntrials,
                             int width_search, float *T_host);
 
-/* Kernel timing: when enabled, every bank-kernel launch of the context is
- * bracketed by HIP events on its stream.  pulscan_ctx_kernel_time waits for
- * the recorded launches, returns their summed duration in milliseconds and
- * their number, and clears the record. */
+/* Kernel timing: with enable = N > 0, every N-th bank-kernel launch of the
+ * context (the first, the N+1-th, ...) is bracketed by HIP events on its
+ * stream; 0 turns timing off, negative values are PULSCAN_EINVAL.  Timing
+ * one launch in N keeps the events' own cost out of most steps.
+ * pulscan_ctx_kernel_time waits for the recorded launches, returns their
+ * summed duration in milliseconds and their number, and clears the
+ * record. */
 int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable);
 int pulscan_ctx_kernel_time(pulscan_ctx *ctx, double *total_ms, uint64_t *launches);
 

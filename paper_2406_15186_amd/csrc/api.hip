@@ -66,8 +66,9 @@ struct pulscan_ctx {
   std::vector<SpecDesc> last_descs;  // what the device descriptor table holds
   DevBuf pdescs;                     // descriptor table of the power pass (harmonic mode)
   std::vector<SpecDesc> last_pdescs;
-  // kernel timing
-  bool timing = false;
+  // kernel timing: every timing-th bank launch (0: off)
+  int timing = 0;
+  uint64_t timing_seen = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
 };
@@ -424,7 +425,8 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   }
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->timing && !power_only && stream != ctx->cap_stream) {
+  if (ctx->timing && !power_only && stream != ctx->cap_stream &&
+      ctx->timing_seen++ % (uint64_t)ctx->timing == 0) {
     e0 = take_event(ctx);
     e1 = take_event(ctx);
     if (!e0 || !e1) return PULSCAN_EHIP;
@@ -1031,7 +1033,9 @@ int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, doub
 
 int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable) {
   if (!ctx) return PULSCAN_EINVAL;
-  ctx->timing = enable != 0;
+  if (enable < 0) return PULSCAN_EINVAL;
+  ctx->timing = enable;
+  ctx->timing_seen = 0;
   if (ctx->timing) {
     // create the events up front so that timed calls do not create any
     HIP_TRY(hipSetDevice(ctx->device));

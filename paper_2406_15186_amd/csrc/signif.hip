@@ -16,15 +16,14 @@ namespace pulscan {
 // log(k!) for an integer k: Stirling's series for k >= 16 (terms through
 // 1/x^7, error below 1e-16 relative there), a table below (the values of
 // log k! rounded to double).
+__constant__ double kLogFactorialSmall[16] = {
+    0.0, 0.0, 0.6931471805599453, 1.791759469228055, 3.1780538303479458, 4.787491742782046,
+    6.579251212010101, 8.525161361065415, 10.60460290274525, 12.801827480081469,
+    15.104412573075516, 17.502307845873887, 19.987214495661885, 22.552163853123425,
+    25.19122118273868, 27.89927138384089};
+
 __device__ double log_factorial(uint32_t k) {
-  if (k < 16) {
-    constexpr double kSmall[16] = {
-        0.0, 0.0, 0.6931471805599453, 1.791759469228055, 3.1780538303479458, 4.787491742782046,
-        6.579251212010101, 8.525161361065415, 10.60460290274525, 12.801827480081469,
-        15.104412573075516, 17.502307845873887, 19.987214495661885, 22.552163853123425,
-        25.19122118273868, 27.89927138384089};
-    return kSmall[k];
-  }
+  if (k < 16) return kLogFactorialSmall[k];
   const double x = (double)k + 1.0, ix = 1.0 / x, ix2 = ix * ix;
   const double series =
       ix * (1.0 / 12.0 - ix2 * (1.0 / 360.0 - ix2 * (1.0 / 1260.0 - ix2 * (1.0 / 1680.0))));
@@ -240,17 +239,18 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
     const SpecDesc &d = p.nspec > 1 ? p.descs[s] : single;
     const uint32_t w = (e.rank_width & ((1u << kWidthBits) - 1u)) + 1u;
     double lp = log_sf_chi2_even((double)e.power, w * d.dofmul) + log(d.ntrials);
-    double sg = sigma_from_logp(lp < 0.0 ? lp : 0.0);
     float pw = e.power;
-    bool keep = true;
-    if (p.fp16 && (sg < (double)p.sigma + kRecheckBand || !(pw < kRecheckPower))) {
-      // within the re-check band (or from saturated FP16 input): the FP32
-      // power decides
+    bool recheck = false;
+    // within the FP16 re-check band, sigma < sigma_req + band, i.e. (sigma
+    // falling as log p rises) log p above log Q(sigma_req + band); or from
+    // saturated FP16 input: the FP32 power decides
+    if (p.fp16 && (lp > log_norm_sf((double)p.sigma + kRecheckBand) || !(pw < kRecheckPower))) {
+      recheck = true;
       pw = power32_window(d, p.block, p.from_power, e.bin, w);
       lp = log_sf_chi2_even((double)pw, w * d.dofmul) + log(d.ntrials);
-      sg = sigma_from_logp(lp < 0.0 ? lp : 0.0);
-      keep = sg >= (double)p.sigma;
     }
+    const double sg = sigma_from_logp(lp < 0.0 ? lp : 0.0);
+    const bool keep = !recheck || sg >= (double)p.sigma;
     pulscan_candidate c;
     c.spectrum = d.spec_id;
     c.bin = p.rblock ? e.bin / p.rblock : e.bin;
