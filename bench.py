@@ -119,6 +119,47 @@ def batched_leg(ctx, pk, synth, args, stream, tone_power):
     torch.cuda.synchronize()
     pms = ev0.elapsed_time(ev1)
     log(f"bench: batched {ms:.3f} ms per batch (graph), plain {pms:.3f} ms for the same spectra")
+
+    # FP16 power storage on the same batch (candidates within the re-check
+    # band of the threshold re-decided on their FP32 power), against the FP32
+    # result above
+    isz = pk.CANDIDATE_DTYPE.itemsize
+    ref = buf[: n0 * isz].cpu().numpy().view(pk.CANDIDATE_DTYPE).copy()
+    hopts = pk.make_opts(async_=True, stream=stream, graph=True, power_fp16=True)
+    hbuf = torch.empty_like(buf)
+    hcnt = torch.zeros_like(cnt)
+
+    def batch16():
+        ctx.pulscan_search_batched(xs, zs, chunk, 6.0, capacity=cap, opts=hopts, out_device=hbuf,
+                                   count_device=hcnt)
+
+    batch16()
+    batch16()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.batch_steps):
+        batch16()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms16 = ev0.elapsed_time(ev1) / args.batch_steps
+    n16 = int(hcnt.item())
+    got = hbuf[: n16 * isz].cpu().numpy().view(pk.CANDIDATE_DTYPE)
+
+    def keyed(c):
+        return {(int(e["spectrum"]), int(e["harmonics"]), int(e["chunk"]), int(e["width"])): e
+                for e in c}
+
+    r, g = keyed(ref), keyed(got)
+    both = set(r) & set(g)
+    rel = max((abs(float(g[k]["power"]) - float(r[k]["power"])) / float(r[k]["power"])
+               for k in both), default=0.0)
+    dsig = max((abs(float(g[k]["sigma"]) - float(r[k]["sigma"])) for k in both), default=0.0)
+    fp16 = {"ms_per_batch": round(ms16, 4), "value": round(bw / (ms16 * 1e-3) / 1e9, 3),
+            "candidates": n16, "only_fp32": len(set(r) - set(g)), "only_fp16": len(set(g) - set(r)),
+            "max_rel_power_diff": float(f"{rel:.3g}"), "max_abs_sigma_diff": float(f"{dsig:.3g}"),
+            "against": "the FP32 batched result (FP32 parity with the oracle is tested)"}
+    log(f"bench: FP16 batch {ms16:.3f} ms, {n16} candidates, {fp16['only_fp32']} only in FP32, "
+        f"{fp16['only_fp16']} only in FP16, max rel power diff {rel:.2e}")
     del xs
     torch.cuda.empty_cache()
     return {"workload": f"dm_trials_{len(wls)}", "spectra": len(wls), "bins": nb,
@@ -127,7 +168,8 @@ def batched_leg(ctx, pk, synth, args, stream, tone_power):
             "hbm_frac": round(8.0 * nb / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "chunk": chunk, "graph": True, "candidates": n0,
             "plain_value": round(bw / (pms * 1e-3) / 1e9, 3), "plain_ms": round(pms, 4),
-            "speedup_vs_plain": round(pms / ms, 3), "autotune_s": round(tune_s, 2)}
+            "speedup_vs_plain": round(pms / ms, 3), "autotune_s": round(tune_s, 2),
+            "fp16": fp16}
 
 
 def serve_stream(pk, pool, rate, seconds, host, max_batch, seed):
@@ -238,6 +280,8 @@ def main():
                     help="duration of the Poisson arrival stream (device-resident spectra); "
                          "0 skips the serving leg")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-copy-peak", dest="copy_peak", action="store_false",
+                    help="skip the 1 GiB device-copy bandwidth measurement")
     ap.add_argument("--copy-reference-mib", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB once on the device, so "
                          "that hardware byte counters can be scaled by a copy of known size")
@@ -324,6 +368,26 @@ def main():
         log(f"bench: copied {args.copy_reference_mib} MiB device to device")
         del src, dst
 
+    # a measured stream-copy peak (a device-to-device copy of 1 GiB, read
+    # plus write), to set the HBM figures against what a plain stream reaches
+    copy_gbs = None
+    if args.copy_peak:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        c1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * (1 << 30) * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        log(f"bench: device copy {copy_gbs:.0f} GB/s (read + write)")
+        del src, dst
+        torch.cuda.empty_cache()
+
     if args.dense:
         # every width evaluated: bounded by the VALU work of the recursion
         achieved = n * Z * BANK_OPS_PER_BIN_WIDTH / (bank_ms * 1e-3) / 1e12
@@ -339,6 +403,9 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "kernel": "bank_kernel", "kernel_us": round(bank_ms * 1e3, 2),
                     "bytes_per_bin": 8}
+        if copy_gbs:
+            roofline["copy_peak"] = round(copy_gbs, 1)
+            roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
 
     cpu = None
     if not args.no_cpu_baseline:

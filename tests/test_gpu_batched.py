@@ -40,16 +40,16 @@ def small_batch(oracle_lib, nspec=6, seed=11):
     return xs, zs
 
 
-@pytest.mark.parametrize("numharm,best", [(1, False), (3, True)])
-def test_graph_replays_match_eager(ctx, pk, oracle_lib, numharm, best):
+@pytest.mark.parametrize("numharm,best,fp16", [(1, False, False), (3, True, False), (1, False, True)])
+def test_graph_replays_match_eager(ctx, pk, oracle_lib, numharm, best, fp16):
     """A graph-mode batched call replays its captured launches; every replay,
     with eager work and synchronisations in between and new data in the same
     buffers, matches an eager call."""
     import torch
     xs, zs = small_batch(oracle_lib)
     ds = [to_device(x) for x in xs]
-    eager_opts = pk.make_opts(numharm=numharm, best_per_chunk=best)
-    graph_opts = pk.make_opts(numharm=numharm, best_per_chunk=best, graph=True)
+    eager_opts = pk.make_opts(numharm=numharm, best_per_chunk=best, power_fp16=fp16)
+    graph_opts = pk.make_opts(numharm=numharm, best_per_chunk=best, graph=True, power_fp16=fp16)
     cap = sum(pk.worst_count(d.shape[0], z, 256, numharm) for d, z in zip(ds, zs))
     for rep in range(4):
         if rep == 2:
