@@ -36,6 +36,7 @@ BANK_SOURCE = os.path.join(ROOT, "paper_2406_15186_amd", "csrc", "bank.hip")
 
 
 TIMING_EVERY = 4  # bank launches per timed one
+SATURATED_REQUESTS = 60000  # the serving capacity run
 
 
 def measured_traffic():
@@ -172,14 +173,19 @@ def batched_leg(ctx, pk, synth, args, stream, tone_power):
             "fp16": fp16}
 
 
-def serve_stream(pk, pool, rate, seconds, host, max_batch, seed):
+def serve_stream(pk, pool, rate, seconds, host, max_batch, seed, count=None):
     """Poisson arrivals at `rate` per second for `seconds`, each a spectrum
-    drawn from `pool` (device tensors, or pinned host pointers if `host`);
-    returns (completed, bin-widths, wall seconds, latencies in ms, launches)."""
+    drawn from `pool` (device tensors, or pinned host pointers if `host`); or,
+    with `count`, that many requests submitted back to back.  Returns
+    (completed, bin-widths, wall seconds, latencies in ms, launches)."""
     import threading
     srv = pk.Server(0, hbm_budget=4 << 30, max_batch=max_batch, chunk=1024, sigma_thresh=6.0)
     rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.5) + 16)
+    if count is not None:
+        gaps = np.zeros(count)
+        seconds = float("inf")
+    else:
+        gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.5) + 16)
     picks = rng.integers(0, len(pool), size=gaps.size)
     sent = []
 
@@ -240,13 +246,20 @@ def serving_leg(pk, synth, args, tone_power):
         host_pool.append((hp, n, 200))
     dev_pool = [(x.data_ptr(), n, z) for x, n, z in pool]
     out = {}
-    for name, p, host, secs, mb in (("device", dev_pool, False, args.serve_seconds, 256),
-                                    ("host", host_pool, True, min(10.0, args.serve_seconds), 256),
-                                    ("device_plain", dev_pool, False, min(10.0, args.serve_seconds), 1)):
-        log(f"bench: serving leg {name}, {secs:.0f} s at {args.serve_rate:.0f}/s")
-        done, work, wall, lat, launches = serve_stream(pk, p, args.serve_rate, secs, host, mb,
-                                                       seed=4)
-        out[name] = {"completed": done, "seconds": round(wall, 2),
+    for name, p, host, secs, mb, rate in (
+            ("device", dev_pool, False, args.serve_seconds, 256, args.serve_rate),
+            ("host", host_pool, True, min(10.0, args.serve_seconds), 256, args.serve_rate),
+            ("device_plain", dev_pool, False, min(10.0, args.serve_seconds), 1, args.serve_rate),
+            # requests submitted back to back: the server's capacity
+            ("device_saturated", dev_pool, False, None, 256, None)):
+        if rate is None:
+            log(f"bench: serving leg {name}, {SATURATED_REQUESTS} requests back to back")
+            done, work, wall, lat, launches = serve_stream(pk, p, 1.0, 0.0, host, mb, seed=4,
+                                                           count=SATURATED_REQUESTS)
+        else:
+            log(f"bench: serving leg {name}, {secs:.0f} s at {rate:.0f}/s")
+            done, work, wall, lat, launches = serve_stream(pk, p, rate, secs, host, mb, seed=4)
+        out[name] = {"completed": done, "seconds": round(wall, 2), "arrivals_per_s": rate,
                      "value": round(work / wall / 1e9, 3), "unit": "G bin-widths/s",
                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
