@@ -35,7 +35,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bank_kernel_plain_2e23_traffic.js
 BANK_SOURCE = os.path.join(ROOT, "paper_2406_15186_amd", "csrc", "bank.hip")
 
 
-TIMING_EVERY = 4  # bank launches per timed one
+TIMING_EVERY = 16  # bank launches per timed one (each timed launch costs ~5 us of step)
 SATURATED_REQUESTS = 60000  # the serving capacity run
 
 
@@ -338,9 +338,9 @@ def main():
     log(f"bench: warmup {args.warmup} done; timing {args.steps} steps")
 
     ctx.pulscan_ctx_kernel_time()
-    # HIP events around every fourth bank launch of the timed steps: their
-    # average is the kernel's duration, and three steps in four carry no
-    # event overhead
+    # HIP events around every TIMING_EVERY-th bank launch of the timed
+    # steps: their average is the kernel's duration, and the other steps
+    # carry no event overhead
     ctx.pulscan_ctx_set_timing(TIMING_EVERY)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)

@@ -332,8 +332,10 @@ class Context:
         return T
 
     # -- timing -----------------------------------------------------------
-    def pulscan_ctx_set_timing(self, enable: bool = True):
-        _check(lib().pulscan_ctx_set_timing(self._ctx, int(bool(enable))), "pulscan_ctx_set_timing")
+    def pulscan_ctx_set_timing(self, enable=True):
+        """Bracket every N-th bank launch with HIP events: True or 1 times every
+        launch, N > 1 every N-th, False or 0 none."""
+        _check(lib().pulscan_ctx_set_timing(self._ctx, int(enable)), "pulscan_ctx_set_timing")
 
     def pulscan_ctx_kernel_time(self):
         """(summed milliseconds, launches) of bank kernels since the last call."""

@@ -317,6 +317,15 @@ def test_kernel_timing_records_launches(ctx, oracle_lib):
     ms, k = ctx.pulscan_ctx_kernel_time()
     ctx.pulscan_ctx_set_timing(False)
     assert k == 3 and ms > 0
+    # every 4th launch: the first, the fifth and the ninth of ten
+    ctx.pulscan_ctx_set_timing(4)
+    for _ in range(10):
+        ctx.pulscan_search_ex(d, wl.zmax, wl.chunk, wl.sigma)
+    ms, k = ctx.pulscan_ctx_kernel_time()
+    ctx.pulscan_ctx_set_timing(0)
+    assert k == 3 and ms > 0
+    with pytest.raises(Exception):
+        ctx.pulscan_ctx_set_timing(-1)
 
 
 # ------------------------------------------------- pruning is exact --------
