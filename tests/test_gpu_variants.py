@@ -46,6 +46,29 @@ def stage_parity(ctx, pk, oracle, x, Z, C, sigma, numharm, label, **kw):
     return got
 
 
+@pytest.mark.parametrize("nbins,Z,C,numharm", [(1 << 16, 64, 256, 1), (1 << 18, 200, 1024, 1),
+                                               (1 << 16, 64, 256, 4)])
+def test_candidate_sigma_at_gpu_power(ctx, pk, oracle_lib, nbins, Z, C, numharm):
+    """Every candidate's significance against the oracle's at the candidate's
+    own FP32 power, dof and trial count: only the significance arithmetic
+    (and the FP32 rounding of the reported value) differs, so they agree far
+    more closely than the search-level tolerance."""
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=nbins)
+    got, cnt = ctx.pulscan_search_ex(to_device(x), Z, C, wl.sigma,
+                                     opts=pk.make_opts(numharm=numharm))
+    assert cnt == len(got) > 0
+    worst = 0.0
+    for c in got:
+        H = int(c["harmonics"])
+        nt = float((nbins // H) * Z)
+        ref = oracle_lib.candidate_sigma(float(c["power"]), int(c["width"]) * H * (H + 1) // 2, nt)
+        worst = max(worst, abs(float(c["sigma"]) - ref) / max(1.0, abs(ref)))
+    say(f"sigma at GPU power n={nbins} Z={Z} H<={numharm}: {len(got)} candidates, "
+        f"max relative difference {worst:.2e}")
+    assert worst <= 2e-6
+
+
 @pytest.mark.parametrize("nbins,Z,C,numharm", [(1 << 16, 64, 256, 4), ((1 << 16) + 123, 64, 256, 3),
                                                (1 << 20, 200, 1024, 4), (5000, 16, 64, 8)])
 def test_harmonic_stages_match_oracle(ctx, pk, oracle_lib, nbins, Z, C, numharm):
