@@ -58,6 +58,9 @@ struct pulscan_ctx {
   // refilled with other contents (thresholds, descriptors, stage jobs)
   uint64_t epoch = 0;
   uint64_t graph_epoch = 0;
+  // a search's bank kernel ran but its count scan was not launched: tile
+  // words may be left published and the pool head advanced
+  bool counts_dirty = false;
   // pinned staging of batched descriptors / threshold jobs
   void *pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -255,6 +258,8 @@ struct Pending {
 // search mode, the emission of the candidates and the best-per-chunk pass.
 // Never waits on the device except to grow a buffer (which a call repeating
 // an earlier one never does), so it can run under stream capture.
+void drop_graph(pulscan_ctx *ctx);
+
 int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a, Pending *pend) {
   hipStream_t stream = (hipStream_t)a.opts.stream;
   const int nspec = (int)specs.size();
@@ -389,6 +394,13 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     st = grow(ctx, ctx->counters, sizeof(Counters), true);
     if (st) return st;
     cnt = static_cast<Counters *>(ctx->counters.p);
+    if (ctx->counts_dirty) {
+      // re-arm what a failed launch left behind (never under capture: a
+      // failure drops the graph, so the next call runs directly)
+      HIP_TRY(hipMemsetAsync(ctx->tile_word.p, 0, ctx->tile_word.bytes, stream));
+      HIP_TRY(hipMemsetAsync(&cnt->head, 0, sizeof(cnt->head), stream));
+      ctx->counts_dirty = false;
+    }
     bp.pool = static_cast<StageEntry *>(ctx->pool.p);
     bp.pool_cap = pool_cap;
     bp.pool_head = &cnt->head;
@@ -451,7 +463,12 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     bs.total2 = bp.total2;
     bs.overflow = bp.overflow;
     bs.lost = &cnt->lost;
-    HIP_TRY(launch_scan_big(bs, stream));
+    if (launch_scan_big(bs, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->counts_dirty = true;
+      drop_graph(ctx);
+      return PULSCAN_EHIP;
+    }
   }
 
   // emit into the caller's device buffer, or into ours for a host copy; with

@@ -552,8 +552,9 @@ constexpr int kSub = 4;  // widths per bound check inside the first width block
 // threshold, or `nblk` if none can.  Powers are non-negative, so every window
 // of width <= w starting at one of the lane's K starts lies in the lane's
 // first w + K - 1 bins, whose sum bounds them all.  The first block (widths
-// 1..K, the lowest thresholds) is checked every kSub widths from the powers
-// themselves; later blocks add one K-bin group sum per block.
+// 1..K, the lowest thresholds) is checked every kSub widths, from the lane's
+// group sum and the next group's powers; later blocks add one K-bin group
+// sum per block.
 // CLAMP: the tile holds -inf past the end of the spectrum; count those as 0.
 template <int K, bool CLAMP, typename PT>
 __device__ __forceinline__ uint32_t bound_lane(const PT *__restrict__ Pl,
@@ -562,30 +563,28 @@ __device__ __forceinline__ uint32_t bound_lane(const PT *__restrict__ Pl,
                                                const float *__restrict__ Tb, uint32_t nblk) {
   constexpr int PITCH = pitch_of<K>();
   constexpr int S = K < kSub ? K : kSub;
-  // the lane's first 2K - 1 bins, summed as they are read
-  const PT *bp = Pl + g * (K * PITCH) + lane;
+  // the first K - 1 bins of the next lane's group
   const uint32_t L1 = lane + 1;
   const PT *bq = Pl + (g + (L1 >> 6)) * (K * PITCH) + (L1 & 63);
-  // every load is issued before the sums use them
-  float v[2 * K - 1];
+  // The lane's own K bins summed from zero in increasing order are its
+  // group sum, Sg[own], exactly (the same order, the same clamp); the next
+  // group's first K - 1 bins are added to it.  Every load is issued before
+  // the sums use them.
+  const uint32_t own = g * 64 + lane;
+  float v[K > 1 ? K - 1 : 1];
 #pragma unroll
-  for (int j = 0; j < K; ++j) v[j] = (float)bp[j * PITCH];
-#pragma unroll
-  for (int u = 1; u < K; ++u) v[K - 1 + u] = (float)bq[(u - 1) * PITCH];
+  for (int u = 1; u < K; ++u) v[u - 1] = (float)bq[(u - 1) * PITCH];
   float t1[(K + S - 1) / S];
 #pragma unroll
   for (int i = 0; i < (K + S - 1) / S; ++i) t1[i] = Tb1[i];
-  float U = 0.f;
-#pragma unroll
-  for (int j = 0; j < K - 1; ++j) U += CLAMP ? clamp0(v[j]) : v[j];
+  float U = Sg[own];
   bool hit = false;
 #pragma unroll
   for (int u = 0; u < K; ++u) {
-    U += CLAMP ? clamp0(v[K - 1 + u]) : v[K - 1 + u];
+    if (u > 0) U += CLAMP ? clamp0(v[u - 1]) : v[u - 1];
     if ((u + 1) % S == 0) hit |= U >= t1[u / S];
   }
   uint32_t fl = hit ? 0u : nblk;
-  const uint32_t own = g * 64 + lane;
   U = Sg[own] + Sg[own + 1];
   // blocks are taken kBoundBatch at a time with their loads issued together
   // (indices clamped to the last block, whose terms are then not used)
