@@ -217,11 +217,17 @@ constexpr int kEmitThreads = 256;
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDesc single) {
   // Each thread's significance is a long dependent chain: the entry's
   // prefix is loaded before it and used only after it.
+  // The first pool entry is requested before the candidate count arrives: the
+  // pool holds pool_cap entries, so the read is in bounds, and its value is
+  // used only when the entry lies below the count.
+  const uint64_t stride = (uint64_t)gridDim.x * kEmitThreads;
+  const uint64_t f0 = (uint64_t)blockIdx.x * kEmitThreads + threadIdx.x;
+  if (f0 >= p.pool_cap) return;
+  const StageEntry e0 = p.pool[f0];
   const unsigned long long total = *p.total;
   const uint64_t lim = total < p.pool_cap ? total : p.pool_cap;
-  const uint64_t stride = (uint64_t)gridDim.x * kEmitThreads;
-  for (uint64_t f = (uint64_t)blockIdx.x * kEmitThreads + threadIdx.x; f < lim; f += stride) {
-    const StageEntry e = p.pool[f];
+  for (uint64_t f = f0; f < lim; f += stride) {
+    const StageEntry e = f == f0 ? e0 : p.pool[f];
     const uint64_t dest = (uint64_t)p.tile_prefix[e.tile] + (e.rank_width >> kWidthBits) +
                           (p.span_prefix ? p.span_prefix[e.tile / kScanSpan] : 0u);
     int s = 0;
