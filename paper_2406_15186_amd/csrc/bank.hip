@@ -800,11 +800,12 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
   uint32_t *items = reinterpret_cast<uint32_t *>(Sg + p.nseg_lds * 64);  // T / K entries
   PT *Pl = reinterpret_cast<PT *>(items + T / K);
 
-  // One tile per workgroup.  Workgroups are dealt round-robin to the 8
-  // XCDs; give each XCD a contiguous run of tiles so the halo a tile shares
-  // with its neighbour is read through the same L2.
-  uint64_t first_tile = blockIdx.x;
-  if ((gridDim.x & 7) == 0) first_tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  // One tile per workgroup, in index order.  (Workgroups are dealt
+  // round-robin to the 8 XCDs, so neighbouring tiles run on different XCDs
+  // and spread their reads over all of them; giving each XCD a contiguous
+  // run of tiles, so that a tile's halo block is read through the L2 that
+  // read it for its neighbour, measured slower.)
+  const uint64_t first_tile = blockIdx.x;
 
   if (first_tile >= p.total_tiles) return;
   {
@@ -832,12 +833,16 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
     const uint32_t bfirst = t0 / B, blast = (t0 + need - 1) / B;
 
     // --- set-up and power --------------------------------------------------
-    // the wave's first block is requested before anything else so that its
-    // memory latency overlaps the set-up
+    // the wave's first block is requested before the rest of the set-up so
+    // that its memory latency overlaps it
     {
     const uint32_t tid = fresh_tid(), lane = tid & 63, wave = tid >> 6;
     BlockData<EPL> bd;
     const bool have = !p.from_power && bfirst + wave <= blast;
+    // loads return in issue order: the thresholds, requested first, are
+    // stored while the block is still in flight
+    const GLOBAL_AS float *gthr = glob(d.thr);
+    const float thr_own = !power_only && tid < zc ? gthr[tid] : 0.f;
     if (have) load_block<EPL>(d.x, n, bfirst + wave, lane, bd);
     if (tid == 0) {
       any_dense = 0u;
@@ -847,20 +852,8 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
     // the pruned search clears the slots only once it has work items
     if (p.dense || p.mode == kModeTables)
       for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
-    const GLOBAL_AS float *gthr = glob(d.thr);
-    for (uint32_t i = tid; i < zc; i += nthr) Tl[i] = gthr[i];
-    if (tid < 4) {
-      constexpr int S = K < kSub ? K : kSub;
-      float m = INFINITY;
-      if (tid * S < (uint32_t)K)
-        for (int u = 0; u < S; ++u) m = fminf(m, gthr[tid * S + u]);
-      Tb1[tid] = m * kBoundSlack;
-    }
-    for (uint32_t i = tid; i < nblk; i += nthr) {
-      float m = gthr[i * K];
-      for (int u = 1; u < K; ++u) m = fminf(m, gthr[i * K + u]);
-      Tb[i] = m * kBoundSlack;
-    }
+    if (tid < zc) Tl[tid] = thr_own;
+    for (uint32_t i = tid + nthr; i < zc; i += nthr) Tl[i] = gthr[i];
     }
     // bins past the spectrum's end are -inf (no window may contain them);
     // halo bins beyond what any width <= zmax reads are 0 (read only by the
@@ -903,6 +896,20 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
           for (int v = 0; v < K; ++v) a += (float)cp[v * PITCH];
         }
         Sg[j] = a;
+      }
+      // the bound's thresholds: minima of the width thresholds (in LDS since
+      // the set-up) over the first block's sub-blocks and over each block
+      if (tid < 4) {
+        constexpr int S = K < kSub ? K : kSub;
+        float m = INFINITY;
+        if (tid * S < (uint32_t)K)
+          for (int u = 0; u < S; ++u) m = fminf(m, Tl[tid * S + u]);
+        Tb1[tid] = m * kBoundSlack;
+      }
+      for (uint32_t i = tid; i < nblk; i += nthr) {
+        float m = Tl[i * K];
+        for (int u = 1; u < K; ++u) m = fminf(m, Tl[i * K + u]);
+        Tb[i] = m * kBoundSlack;
       }
       __syncthreads();
     }
