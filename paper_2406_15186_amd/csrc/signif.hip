@@ -35,23 +35,29 @@ __device__ double log_sf_chi2_even(double x, uint32_t w) {
   const double y = 0.5 * x;
   const uint32_t kp = (y >= (double)(w - 1)) ? w - 1 : (uint32_t)floor(y);
   const double log_peak = (double)kp * log(y) - log_factorial(kp);
-  // Terms are taken four at a time: the products of four ratios do not
+  // Terms are taken several at a time: the products of the ratios do not
   // depend on the running term, so the dependent chain advances one
-  // multiplication per four terms (one candidate per thread, few threads:
-  // the chain's latency is the kernel's time).
+  // multiplication per step (one candidate per thread, few threads: the
+  // chain's latency is the kernel's time).  Below the peak, where the long
+  // runs are, eight terms a step; above it, four.
   double acc = 1.0, r = 1.0;
   const double iy = 1.0 / y;
   uint32_t k = kp;
-  for (; k >= 4; k -= 4) {  // terms below the peak shrink by k / y
-    const double a1 = (double)k * iy, a2 = (double)(k - 1) * iy;
-    const double a3 = (double)(k - 2) * iy, a4 = (double)(k - 3) * iy;
-    const double b12 = a1 * a2, b123 = b12 * a3, b1234 = b12 * (a3 * a4);
-    const double r1 = r * a1, r2 = r * b12, r3 = r * b123, r4 = r * b1234;
-    acc += (r1 + r2) + (r3 + r4);
-    r = r4;
+  for (; k >= 8; k -= 8) {  // terms below the peak shrink by k / y
+    double a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = (double)(k - j) * iy;
+    const double b12 = a[0] * a[1], b34 = a[2] * a[3], b56 = a[4] * a[5], b78 = a[6] * a[7];
+    const double b1234 = b12 * b34, b5678 = b56 * b78;
+    const double p3 = b12 * a[2], p5 = b1234 * a[4], p6 = b1234 * b56;
+    const double p7 = p6 * a[6], p8 = b1234 * b5678;
+    const double s14 = (r * a[0] + r * b12) + (r * p3 + r * b1234);
+    const double s58 = (r * p5 + r * p6) + (r * p7 + r * p8);
+    acc += s14 + s58;
+    r *= p8;
     if (r < 1e-18 * acc) break;
   }
-  if (k < 4 && !(r < 1e-18 * acc)) {
+  if (k < 8 && !(r < 1e-18 * acc)) {
     for (; k >= 1; --k) {
       r *= (double)k * iy;
       acc += r;
