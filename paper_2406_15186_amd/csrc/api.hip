@@ -505,7 +505,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     ep.capacity = pool_cap;
   }
   const uint64_t work = ep.capacity < worst ? ep.capacity : worst;
-  const uint32_t egrid = (uint32_t)(work / 256 + 1 < 512 ? work / 256 + 1 : 512);
+  const uint32_t egrid = (uint32_t)(work / 64 + 1 < 2048 ? work / 64 + 1 : 2048);
   HIP_TRY(launch_emit(ep, descs[0], egrid, stream));
   if (fin)
     HIP_TRY(launch_finalize(ep.out, bp.total, pool_cap, dst, cap, &cnt->best,

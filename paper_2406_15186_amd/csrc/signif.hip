@@ -230,7 +230,9 @@ __device__ float power32_window(const SpecDesc &d, uint32_t B, int from_power, u
 // Emit: pool entry f (tile, rank) goes to its canonical place, the tile's
 // exclusive prefix plus its rank, with its Gaussian-equivalent sigma.
 
-constexpr int kEmitThreads = 256;
+// One wave per workgroup: the few candidate chains of a search then run on
+// as many CUs as there are waves, none sharing a CU's instruction fetch.
+constexpr int kEmitThreads = 64;
 
 __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDesc single) {
   // Each thread's significance is a long dependent chain: the entry's
