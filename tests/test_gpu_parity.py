@@ -148,8 +148,12 @@ def test_search_plain_2e23(ctx, oracle_lib):
     assert len(cands) > 100
 
 
+# the last two are the largest zmax that the 64 KiB of LDS per workgroup
+# admit with FP32 power: 2048, with 1024-bin chunks and blocks (one-block
+# tiles, two halo blocks) and with 4096-bin chunks and blocks
 @pytest.mark.parametrize("n,Z,C", [(1 << 14, 1, 256), (1 << 14, 256, 256), (256, 64, 256),
-                                   (1024 + 64, 64, 1024), (20000, 100, 64)])
+                                   (1024 + 64, 64, 1024), (20000, 100, 64),
+                                   (3 * 1024 + 517, 2048, 1024), (2 * 4096 + 333, 2048, 4096)])
 def test_search_edge_shapes(ctx, oracle_lib, n, Z, C):
     wl = synth.workload("plain_2e16")
     x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=n)

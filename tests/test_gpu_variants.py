@@ -270,6 +270,41 @@ def test_fp16_pruned_equals_dense_and_batched(ctx, pk, oracle_lib):
     assert n == len(ref) and (got == ref).all()
 
 
+def test_fp16_admits_the_largest_chunk(ctx, pk, oracle_lib):
+    """A 16384-bin chunk (with 1024-bin normalisation blocks) needs more LDS
+    than a workgroup has with FP32 power and fits with FP16: one 16384-bin
+    tile, its 17 blocks normalised by 8 waves (two or three each)."""
+    n = 2 * 16384 + 123
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=n)
+    d = to_device(x)
+    with pytest.raises(pk.PulscanError) as e:
+        ctx.pulscan_search_ex(d, 200, 16384, 6.0, opts=pk.make_opts(norm_block=1024))
+    assert e.value.status == pk.PULSCAN_EUNSUPPORTED
+    got, cnt = ctx.pulscan_search_ex(d, 200, 16384, 6.0,
+                                     opts=pk.make_opts(norm_block=1024, power_fp16=True))
+    assert cnt == len(got) > 0
+    orc = oracle_lib.search(x, 200, 16384, 6.0, norm_block=1024)
+    fp16_diff(got, orc, 6.0, f"fp16 n={n} C=16384")
+
+
+def test_fp16_admits_the_largest_zmax(ctx, pk, oracle_lib):
+    """zmax 4096 with 1024-bin chunks needs about 72 KiB of LDS per
+    workgroup with FP32 power (its 64-bit maxima and thresholds alone
+    48 KiB), so it is refused; with FP16 power it fits."""
+    n = 5 * 1024 + 517
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=n)
+    d = to_device(x)
+    with pytest.raises(pk.PulscanError) as e:
+        ctx.pulscan_search_ex(d, 4096, 1024, 6.0)
+    assert e.value.status == pk.PULSCAN_EUNSUPPORTED
+    got, cnt = ctx.pulscan_search_ex(d, 4096, 1024, 6.0, opts=pk.make_opts(power_fp16=True))
+    assert cnt == len(got) > 0
+    orc = oracle_lib.search(x, 4096, 1024, 6.0)
+    fp16_diff(got, orc, 6.0, f"fp16 n={n} Z=4096")
+
+
 def test_fp16_unsupported_with_4096_blocks(ctx, pk):
     import torch
     d = torch.zeros((1 << 14, 2), dtype=torch.float32, device="cuda")
