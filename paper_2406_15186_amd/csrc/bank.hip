@@ -839,8 +839,9 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
     const uint32_t tid = fresh_tid(), lane = tid & 63, wave = tid >> 6;
     BlockData<EPL> bd;
     const bool have = !p.from_power && bfirst + wave <= blast;
-    // loads return in issue order: the thresholds, requested first, are
-    // stored while the block is still in flight
+    // the thresholds (one per thread) are requested with the block; the
+    // bound's minima of them come later from LDS, so the set-up makes no
+    // further round trip to memory
     const GLOBAL_AS float *gthr = glob(d.thr);
     const float thr_own = !power_only && tid < zc ? gthr[tid] : 0.f;
     if (have) load_block<EPL>(d.x, n, bfirst + wave, lane, bd);
