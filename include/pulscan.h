@@ -118,7 +118,8 @@ typedef struct {
   double ntrials;       /* Bonferroni trials; 0 = nbins * searched widths            */
   int32_t width_search; /* PULSCAN_W_ALL (default): widths 1..zmax.
                            PULSCAN_W_LOG2: only widths w with z = w - 1 a power of
-                           two (2, 3, 5, 9, 17, ...), section 4.1.3; every width
+                           two (2, 3, 5, 9, 17, ...) and the widest width zmax,
+                           section 4.1.3 (z = 1, 2, 4, ... z-max); every width
                            is still summed, the others are just not searched        */
   int32_t async;        /* 0 (default): wait for the stream and set out->count.
                            1: enqueue only; needs out->on_device and

@@ -89,8 +89,12 @@ def lib():
         L.oracle_search_harm.restype = i64
         L.oracle_search_harm.argtypes = [fp, i64, ctypes.c_int, i64, ctypes.c_double, i64,
                                          ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                         i64, ctypes.POINTER(_Cand), dp,
+                                         i64, i64, ctypes.POINTER(_Cand), dp,
                                          ctypes.POINTER(ctypes.c_int64), dp]
+        L.oracle_width_is_searched.restype = ctypes.c_int
+        L.oracle_width_is_searched.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_rblock_index.restype = i64
+        L.oracle_rblock_index.argtypes = [i64, i64]
         L.oracle_harmonic_sum.restype = i64
         L.oracle_harmonic_sum.argtypes = [dp, i64, ctypes.c_int, dp]
         L.oracle_num_threads.restype = ctypes.c_int
@@ -221,12 +225,23 @@ W_ALL = 0
 W_LOG2 = 1
 
 
+def width_is_searched(w: int, zmax: int, width_search: int = W_ALL) -> bool:
+    """Is width w of a 1..zmax bank searched for candidates (section 4.1.3)?"""
+    return bool(lib().oracle_width_is_searched(int(w), int(zmax), int(width_search)))
+
+
+def rblock_index(b: int, rblock: int) -> int:
+    """The location an R-Block search reports for window start b (section 2.4)."""
+    return int(lib().oracle_rblock_index(int(b), int(rblock)))
+
+
 def search(spec, zmax: int, chunk: int, sigma: float, norm_block: int = 0, mode: int = NORM_MOM,
            ntrials: float = 0.0, tables: bool = False, cap: int = None,
-           width_search: int = W_ALL, numharm: int = 1) -> SearchResult:
+           width_search: int = W_ALL, numharm: int = 1, rblock: int = 0) -> SearchResult:
     """Full search of one spectrum; candidates in (stage, chunk, width) order.
     With numharm > 1 the harmonic stages H = 1..numharm are searched and each
-    candidate carries its stage in ``harm``; tables are those of stage 1."""
+    candidate carries its stage in ``harm``; tables are those of stage 1.
+    With rblock > 0 each candidate's ``bin`` is its r-block index (R-Block)."""
     s = _as_spec(spec)
     n = s.shape[0]
     nc = (n + chunk - 1) // chunk
@@ -242,7 +257,7 @@ def search(spec, zmax: int, chunk: int, sigma: float, norm_block: int = 0, mode:
         mp, ip, pp = _dptr(M), I.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(P)
     cnt = lib().oracle_search_harm(s.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, zmax,
                                    chunk, sigma, norm_block, mode, ntrials, width_search,
-                                   max(int(numharm), 1), cap,
+                                   max(int(numharm), 1), int(rblock), cap,
                                    out.ctypes.data_as(ctypes.POINTER(_Cand)), mp, ip, pp)
     if cnt < 0:
         raise ValueError("oracle_search rejected its arguments")

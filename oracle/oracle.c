@@ -335,12 +335,14 @@ typedef struct {
 } oracle_candidate;
 
 /* Widths searched for candidates (all are summed): every width (mode 0), or
- * only those whose drift z = w - 1 is a power of two (mode 1, the
- * logarithmic z sampling of section 4.1.3: z = 1, 2, 4, 8, ...). */
-static int width_is_searched(int w, int width_search) {
+ * the logarithmic z sampling of section 4.1.3 (mode 1), whose list runs
+ * z = 1, 2, 4, 8, ... and ends at z-max: the widths whose drift z = w - 1 is
+ * a power of two, plus the widest width zmax itself. */
+int oracle_width_is_searched(int w, int zmax, int width_search) {
+  if (w < 1 || w > zmax) return 0;
   if (width_search == 1) {
     int z = w - 1;
-    return z > 0 && (z & (z - 1)) == 0;
+    return w == zmax || (z > 0 && (z & (z - 1)) == 0);
   }
   return 1;
 }
@@ -367,6 +369,15 @@ int64_t oracle_harmonic_sum(const double *P, int64_t n, int H, double *S) {
   return m;
 }
 
+/* Location a candidate reports (section 2.4, "Approximate r-bin location"):
+ * the exact r-bin of its window's left edge, or, in the R-Block variant
+ * (rblock > 0), only the index of the rblock-bin block holding that edge,
+ * floor(bin / rblock).  The candidate itself (its chunk, width, power and
+ * significance) is the same in both variants. */
+int64_t oracle_rblock_index(int64_t bin, int64_t rblock) {
+  return rblock > 0 ? bin / rblock : bin;
+}
+
 /* Search one power series (one harmonic stage): per-chunk maxima of every
  * width, significance with H(H+1) w degrees of freedom (a width-w boxcar of
  * chi^2(H(H+1)) values), and emission of the maxima of searched widths whose
@@ -374,8 +385,9 @@ int64_t oracle_harmonic_sum(const double *P, int64_t n, int H, double *S) {
  * Appends to out (at most cap - *count entries) and advances *count by the
  * number found. */
 static int search_stage(const double *S, int64_t m, int H, int zmax, int64_t chunk,
-                        double sigma_thresh, double ntrials, int width_search, int64_t cap,
-                        oracle_candidate *out, int64_t *count, double *M_out, int64_t *I_out) {
+                        double sigma_thresh, double ntrials, int width_search, int64_t rblock,
+                        int64_t cap, oracle_candidate *out, int64_t *count, double *M_out,
+                        int64_t *I_out) {
   int64_t nchunks = (m + chunk - 1) / chunk;
   double *M = M_out ? M_out : (double *)malloc((size_t)(nchunks * zmax) * sizeof(double));
   int64_t *I = I_out ? I_out : (int64_t *)malloc((size_t)(nchunks * zmax) * sizeof(int64_t));
@@ -391,12 +403,13 @@ static int search_stage(const double *S, int64_t m, int H, int zmax, int64_t chu
       lp[e] = I[e] >= 0 ? oracle_log_p_corrected(M[e], w * dof_half, ntrials) : 0.0;
     }
     for (int64_t e = 0; e < nchunks * zmax; ++e) {
-      if (I[e] < 0 || !width_is_searched((int)(e % zmax) + 1, width_search)) continue;
+      if (I[e] < 0 || !oracle_width_is_searched((int)(e % zmax) + 1, zmax, width_search))
+        continue;
       if (!(lp[e] <= lthresh) || !(lp[e] < 0.0)) continue;
       if (*count < cap && out) {
         oracle_candidate *o = &out[*count];
         o->chunk = e / zmax;
-        o->bin = I[e];
+        o->bin = oracle_rblock_index(I[e], rblock);
         o->width = (int32_t)(e % zmax) + 1;
         o->harm = H;
         o->power = M[e];
@@ -417,21 +430,22 @@ static int search_stage(const double *S, int64_t m, int H, int zmax, int64_t chu
  * boxcars, per-chunk maxima and threshold.  Emits, in (stage, chunk, width)
  * order, every per-chunk maximum of a searched width whose corrected
  * significance reaches sigma_thresh.  ntrials <= 0 means, per stage, the
- * stage's length times the number of searched widths.  Writes at most `cap`
+ * stage's length times the number of searched widths.  rblock > 0 reports
+ * each candidate's r-block index instead of its r-bin.  Writes at most `cap`
  * candidates to `out` and returns the total count, or -1 on invalid
  * arguments or allocation failure.  If M_out / I_out are non-null they
  * receive the (nchunks x zmax) maxima tables of stage 1 and P_out the
  * normalised power. */
 int64_t oracle_search_harm(const float *spec, int64_t n, int zmax, int64_t chunk,
                            double sigma_thresh, int64_t norm_block, int mode, double ntrials,
-                           int width_search, int numharm, int64_t cap, oracle_candidate *out,
-                           double *M_out, int64_t *I_out, double *P_out) {
-  if (!spec || n < 1 || zmax < 1 || chunk < 1) return -1;
+                           int width_search, int numharm, int64_t rblock, int64_t cap,
+                           oracle_candidate *out, double *M_out, int64_t *I_out, double *P_out) {
+  if (!spec || n < 1 || zmax < 1 || chunk < 1 || rblock < 0) return -1;
   if (numharm < 1) numharm = 1;
   if (norm_block <= 0) norm_block = chunk;
   if (norm_block > n || zmax > n) return -1;
   int searched = 0;
-  for (int w = 1; w <= zmax; ++w) searched += width_is_searched(w, width_search);
+  for (int w = 1; w <= zmax; ++w) searched += oracle_width_is_searched(w, zmax, width_search);
   if (searched == 0) searched = 1;
   double *re = (double *)malloc((size_t)n * sizeof(double));
   double *im = (double *)malloc((size_t)n * sizeof(double));
@@ -451,8 +465,8 @@ int64_t oracle_search_harm(const float *spec, int64_t n, int zmax, int64_t chunk
     }
     if (m < 1) break;
     double nt = ntrials > 0.0 ? ntrials : (double)m * searched;
-    if (search_stage(X, m, H, zmax, chunk, sigma_thresh, nt, width_search, cap, out, &count,
-                     H == 1 ? M_out : NULL, H == 1 ? I_out : NULL) != 0) {
+    if (search_stage(X, m, H, zmax, chunk, sigma_thresh, nt, width_search, rblock, cap, out,
+                     &count, H == 1 ? M_out : NULL, H == 1 ? I_out : NULL) != 0) {
       count = -1;
       goto done;
     }
@@ -470,7 +484,7 @@ int64_t oracle_search(const float *spec, int64_t n, int zmax, int64_t chunk, dou
                       int64_t norm_block, int mode, double ntrials, int width_search, int64_t cap,
                       oracle_candidate *out, double *M_out, int64_t *I_out, double *P_out) {
   return oracle_search_harm(spec, n, zmax, chunk, sigma_thresh, norm_block, mode, ntrials,
-                            width_search, 1, cap, out, M_out, I_out, P_out);
+                            width_search, 1, 0, cap, out, M_out, I_out, P_out);
 }
 
 /* Number of OpenMP threads a parallel region of this library uses. */

@@ -166,7 +166,7 @@ bool is_pow4(uint64_t v) {
 
 uint32_t searched_widths(uint32_t zmax, int ws) {
   uint32_t c = 0;
-  for (uint32_t w = 1; w <= zmax; ++w) c += width_searched(w, ws) ? 1u : 0u;
+  for (uint32_t w = 1; w <= zmax; ++w) c += width_searched(w, zmax, ws) ? 1u : 0u;
   return c;
 }
 

@@ -213,11 +213,14 @@ inline uint64_t harmonic_offset(uint64_t n, uint32_t H) {
 }
 constexpr int kMaxHarm = 16;
 
-// Is width w searched under width_search?
-__host__ __device__ inline bool width_searched(uint32_t w, int width_search) {
+// Is width w of a 1..zmax bank searched under width_search?  The
+// logarithmic z sampling (section 4.1.3) searches z = w - 1 = 1, 2, 4, ...
+// and the largest drift, i.e. the widest width zmax itself.
+__host__ __device__ inline bool width_searched(uint32_t w, uint32_t zmax, int width_search) {
+  if (w < 1 || w > zmax) return false;
   if (width_search == PULSCAN_W_LOG2) {
-    uint32_t z = w - 1;
-    return z != 0 && (z & (z - 1)) == 0;
+    const uint32_t z = w - 1;
+    return w == zmax || (z != 0 && (z & (z - 1)) == 0);
   }
   return true;
 }

@@ -183,7 +183,7 @@ __global__ void threshold_kernel(const ThreshJob *__restrict__ jobs, ThreshJob s
   const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x + 1;
   if (w > jb.zc) return;
   float out;
-  if (w > jb.zmax || !width_searched(w, width_search))
+  if (!width_searched(w, jb.zmax, width_search))
     out = INFINITY;
   else if (debug)
     out = -FLT_MAX;

@@ -180,16 +180,23 @@ def test_search_pure_noise_is_quiet(ctx, oracle_lib):
     assert count == 0
 
 
-def test_log2_width_search(ctx, pk, oracle_lib):
+@pytest.mark.parametrize("zmax,widths", [(64, [2, 3, 5, 9, 17, 33, 64]),
+                                          (100, [2, 3, 5, 9, 17, 33, 65, 100])])
+def test_log2_width_search(ctx, pk, oracle_lib, zmax, widths):
+    """Logarithmic z sampling (z = 1, 2, 4, ... z-max): the searched widths,
+    the trial count and the candidates match the oracle's."""
     wl = synth.workload("plain_2e16")
     x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
     opts = pk.make_opts(width_search=pk.PULSCAN_W_LOG2)
-    cands, count = ctx.pulscan_search_ex(to_device(x), wl.zmax, wl.chunk, wl.sigma, opts=opts)
-    orc = oracle_lib.search(x, wl.zmax, wl.chunk, wl.sigma, tables=True,
+    cands, count = ctx.pulscan_search_ex(to_device(x), zmax, wl.chunk, wl.sigma, opts=opts)
+    orc = oracle_lib.search(x, zmax, wl.chunk, wl.sigma, tables=True,
                             width_search=oracle_lib.W_LOG2)
-    nt = float(wl.nbins * 6)
-    compare_candidates(cands, orc, orc.P, nt, wl.sigma, oracle_lib, "log2")
-    assert set(cands["width"].tolist()) <= {2, 3, 5, 9, 17, 33}
+    nt = float(wl.nbins * len(widths))
+    compare_candidates(cands, orc, orc.P, nt, wl.sigma, oracle_lib, f"log2 zmax {zmax}")
+    assert set(cands["width"].tolist()) <= set(widths)
+    assert zmax in set(orc.cands["width"].tolist())  # the endpoint finds something here
+    T = ctx.pulscan_threshold_table(zmax, wl.sigma, nt, width_search=pk.PULSCAN_W_LOG2)
+    assert [w for w in range(1, zmax + 1) if np.isfinite(T[w - 1])] == widths
 
 
 # ------------------------------------------------------- API behaviours --

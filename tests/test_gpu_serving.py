@@ -1,7 +1,7 @@
 """GPU checks of the serving runtime: spectra submitted one by one (device-
 resident or in pinned host memory) come back with the candidates the plain
-search finds for them, in any admission grouping the device budget forces,
-with ordered timestamps."""
+search finds for them, and the oracle's, in any admission grouping the
+device budget forces, with ordered timestamps."""
 
 import ctypes
 import time
@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import say, to_device
+from gpu_helpers import compare_candidates, say, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -84,6 +84,12 @@ def test_served_results_match_plain_searches(ctx, pk, oracle_lib, budget_spectra
             ref, rc = ctx.pulscan_search_ex(dev[i], specs[i][1], 1024, 6.0)
             assert total == rc == len(cands)
             assert (cands == ref).all(), i
+            if i < 2:
+                # one device-resident and one host spectrum against the oracle
+                x, z = specs[i]
+                orc = oracle_lib.search(x, z, 1024, 6.0, tables=True)
+                compare_candidates(cands, orc, orc.P, float(x.shape[0] * z), 6.0, oracle_lib,
+                                   f"served {'device' if i % 2 == 0 else 'host'} spectrum {i}")
     finally:
         srv.close()
         for p in host:

@@ -114,6 +114,35 @@ def test_harmonic_batched_equals_plain(ctx, pk, oracle_lib):
     assert len(ref) == len(got) and (ref == got).all()
 
 
+@pytest.mark.parametrize("numharm,rb", [(1, 1000), (1, 256), (2, 4096)])
+def test_rblock_matches_the_oracle(ctx, pk, oracle_lib, numharm, rb):
+    """R-Block (section 2.4): the GPU's reported block indices against the
+    oracle's R-Block search of the same spectrum."""
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    d = to_device(x)
+    got, _ = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(numharm=numharm, rblock=rb))
+    exact, _ = ctx.pulscan_search_ex(d, 64, 256, 6.0, opts=pk.make_opts(numharm=numharm))
+    orc = oracle_lib.search(x, 64, 256, 6.0, numharm=numharm, rblock=rb)
+    orc_exact = oracle_lib.search(x, 64, 256, 6.0, numharm=numharm)
+    key = lambda c: (int(c["harmonics"] if "harmonics" in c.dtype.names else c["harm"]),
+                     int(c["chunk"]), int(c["width"]))
+    g = {key(c): c for c in got}
+    ge = {key(c): c for c in exact}
+    o = {key(c): c for c in orc.cands}
+    oe = {key(c): c for c in orc_exact.cands}
+    # candidates away from the threshold are the oracle's
+    for k in set(g) ^ set(o):
+        s = float(o[k]["sigma"]) if k in o else float(g[k]["sigma"])
+        assert abs(s - 6.0) < 1e-3, (k, s)
+    assert len(set(g) & set(o)) > 0
+    for k in set(g) & set(o):
+        assert abs(float(g[k]["power"]) - o[k]["power"]) <= 1e-5 * o[k]["power"], k
+        if int(ge[k]["bin"]) == int(oe[k]["bin"]):  # same argmax: same block
+            assert int(g[k]["bin"]) == int(o[k]["bin"]), k
+        assert int(g[k]["bin"]) == int(ge[k]["bin"]) // rb, k
+
+
 def test_rblock_reports_block_indices(ctx, pk, oracle_lib):
     wl = synth.workload("plain_2e16")
     x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)

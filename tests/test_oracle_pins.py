@@ -355,17 +355,34 @@ def test_emission_rule_matches_scipy(oracle_lib):
     assert len(r.cands) > 0
 
 
+@pytest.mark.parametrize("zmax,widths", [
+    (64, [2, 3, 5, 9, 17, 33, 64]),
+    (200, [2, 3, 5, 9, 17, 33, 65, 129, 200]),
+    (33, [2, 3, 5, 9, 17, 33]),
+    (2, [2]),
+    (1, [1]),
+])
+def test_log_width_list_ends_at_zmax(oracle_lib, zmax, widths):
+    """Section 4.1.3 lists the searched drifts as z = 1, 2, 4, 8, ... z-max:
+    the powers of two, then the largest drift.  With widths 1..zmax and
+    z = w - 1 that is w = 2, 3, 5, 9, ... and the widest width zmax itself
+    (written out here by hand for each zmax)."""
+    got = [w for w in range(1, zmax + 1) if oracle_lib.width_is_searched(w, zmax, oracle_lib.W_LOG2)]
+    assert got == widths
+    assert all(oracle_lib.width_is_searched(w, zmax, oracle_lib.W_ALL) for w in range(1, zmax + 1))
+    assert not oracle_lib.width_is_searched(zmax + 1, zmax, oracle_lib.W_ALL)
+
+
 def test_log_width_sampling(oracle_lib):
-    """Section 4.1.3: only z = w - 1 in {1, 2, 4, 8, ...} is searched, and the
-    Bonferroni factor counts only those widths."""
+    """Section 4.1.3: only z = w - 1 in {1, 2, 4, 8, ..., z-max} is searched,
+    and the Bonferroni factor counts only those widths."""
     import synth
     wl = synth.workload("plain_2e16")
     x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
     Z = wl.zmax
     full = oracle_lib.search(x, Z, wl.chunk, wl.sigma, tables=True)
     logz = oracle_lib.search(x, Z, wl.chunk, wl.sigma, width_search=oracle_lib.W_LOG2)
-    searched = [w for w in range(1, Z + 1) if (w - 1) > 0 and ((w - 1) & (w - 2)) == 0]
-    assert searched == [2, 3, 5, 9, 17, 33]
+    searched = [2, 3, 5, 9, 17, 33, 64]
     assert set(logz.cands["width"].tolist()) <= set(searched)
     nt = float(wl.nbins * len(searched))
     expect = []
@@ -476,3 +493,35 @@ def test_harmonic_summing_recovers_a_multi_harmonic_signal(oracle_lib):
     assert not (near & (c["harm"] == 1)).any()
     hit = c[near & (c["harm"] == 4)]
     assert len(hit) > 0 and np.abs(hit["width"].astype(int) - w).min() <= 2
+
+
+# ---------------------------------------------------------------- R-Block --
+
+def test_rblock_reports_block_index_of_the_same_candidates(oracle_lib):
+    """Section 2.4: the R-Block variant keeps only the index of the block of
+    r-bins a candidate lies in.  The candidates themselves do not change; with
+    a block as wide as the chunk the reported index is the chunk's own index
+    (the argmax window starts inside its chunk), with rblock 1 it is the
+    exact bin."""
+    import synth
+    wl = synth.workload("plain_2e16")
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma)
+    exact = oracle_lib.search(x, wl.zmax, wl.chunk, wl.sigma, tables=True)
+    assert len(exact.cands) > 0
+    for c in exact.cands:  # the exact bin is the table's argmax, inside the chunk
+        assert exact.I[c["chunk"], c["width"] - 1] == c["bin"]
+        assert c["chunk"] * wl.chunk <= c["bin"] < (c["chunk"] + 1) * wl.chunk
+    for rb in (1, wl.chunk, 1000, 32768):
+        r = oracle_lib.search(x, wl.zmax, wl.chunk, wl.sigma, rblock=rb)
+        assert len(r.cands) == len(exact.cands)
+        for f in ("chunk", "width", "harm", "power", "sigma", "logp"):
+            np.testing.assert_array_equal(r.cands[f], exact.cands[f])
+        if rb == 1:
+            np.testing.assert_array_equal(r.cands["bin"], exact.cands["bin"])
+        if rb == wl.chunk:
+            np.testing.assert_array_equal(r.cands["bin"], exact.cands["chunk"])
+        # brute force: the block whose bin range holds the exact bin
+        for a, b in zip(r.cands, exact.cands):
+            assert a["bin"] * rb <= b["bin"] < (a["bin"] + 1) * rb
+    with pytest.raises(ValueError):
+        oracle_lib.search(x, wl.zmax, wl.chunk, wl.sigma, rblock=-1)
