@@ -238,6 +238,23 @@ int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, doub
 int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable);
 int pulscan_ctx_kernel_time(pulscan_ctx *ctx, double *total_ms, uint64_t *launches);
 
+/* Which bank kernel the context launches.  kernel = PULSCAN_KERNEL_STREAM
+ * (the default): the streaming kernel (persistent workgroups, each reading a
+ * contiguous range of normalisation blocks once) for every search and
+ * debug-table call it serves, the tiled kernel (one workgroup per tile, each
+ * tile re-reading the block after it) for the rest; PULSCAN_KERNEL_TILED: the
+ * tiled kernel always.  Both give the same candidates within the stated
+ * tolerances (the FP32 summation orders differ).  EINVAL for other values. */
+enum { PULSCAN_KERNEL_STREAM = 0, PULSCAN_KERNEL_TILED = 1 };
+int pulscan_ctx_set_kernel(pulscan_ctx *ctx, int kernel);
+
+/* Polls of a word another workgroup publishes (a count, or the statistics of
+ * a halo block) before the streaming kernel gives up on it: a lost count
+ * makes the search return PULSCAN_EHIP, a lost statistics word is recomputed
+ * from the spectrum.  Default 2^20 (a hundred milliseconds or more); a small
+ * value forces the give-up paths in tests.  polls >= 1, else EINVAL. */
+int pulscan_ctx_set_spin(pulscan_ctx *ctx, uint32_t polls);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: spectra searched as they arrive.                                */
 /* ---------------------------------------------------------------------- */

@@ -29,6 +29,8 @@ PULSCAN_NORM_MOM = 0
 PULSCAN_NORM_EXACT = 1
 PULSCAN_W_ALL = 0
 PULSCAN_W_LOG2 = 1
+PULSCAN_KERNEL_STREAM = 0
+PULSCAN_KERNEL_TILED = 1
 
 
 class pulscan_candidate(ctypes.Structure):
@@ -97,6 +99,8 @@ SIGNATURES = {
     "pulscan_threshold_table": (_i, [_vp, _i, _f, _d, _i, ctypes.POINTER(ctypes.c_float)]),
     "pulscan_ctx_set_timing": (_i, [_vp, _i]),
     "pulscan_ctx_kernel_time": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint64)]),
+    "pulscan_ctx_set_kernel": (_i, [_vp, _i]),
+    "pulscan_ctx_set_spin": (_i, [_vp, ctypes.c_uint32]),
     "pulscan_server_config_default": (None, [ctypes.POINTER(pulscan_server_config)]),
     "pulscan_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(pulscan_server_config)]),
     "pulscan_server_destroy": (None, [_vp]),
@@ -336,6 +340,14 @@ class Context:
         """Bracket every N-th bank launch with HIP events: True or 1 times every
         launch, N > 1 every N-th, False or 0 none."""
         _check(lib().pulscan_ctx_set_timing(self._ctx, int(enable)), "pulscan_ctx_set_timing")
+
+    def pulscan_ctx_set_kernel(self, kernel: int):
+        """PULSCAN_KERNEL_STREAM (default) or PULSCAN_KERNEL_TILED."""
+        _check(lib().pulscan_ctx_set_kernel(self._ctx, int(kernel)), "pulscan_ctx_set_kernel")
+
+    def pulscan_ctx_set_spin(self, polls: int):
+        """Polls of a cross-workgroup word before the streaming kernel gives up."""
+        _check(lib().pulscan_ctx_set_spin(self._ctx, int(polls)), "pulscan_ctx_set_spin")
 
     def pulscan_ctx_kernel_time(self):
         """(summed milliseconds, launches) of bank kernels since the last call."""

@@ -11,7 +11,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libpulscan.so")
-SOURCES = ["api.hip", "bank.hip", "signif.hip", "harmonic.hip", "serve.hip"]
+SOURCES = ["api.hip", "bank.hip", "stream.hip", "signif.hip", "harmonic.hip", "serve.hip"]
+# Translation units built without NaN semantics (their inputs are finite):
+# the compiler may then fold cross-lane moves into DPP min/max instructions.
+NO_NANS = {"stream.hip"}
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -20,7 +23,8 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
 
 def _compile(src: str) -> str:
     obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-fno-honor-nans"] if src in NO_NANS else []
+    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

@@ -69,6 +69,13 @@ struct pulscan_ctx {
   std::vector<SpecDesc> last_descs;  // what the device descriptor table holds
   DevBuf pdescs;                     // descriptor table of the power pass (harmonic mode)
   std::vector<SpecDesc> last_pdescs;
+  // streaming kernel: per-workgroup counts and prefixes, the launch
+  // generation and the published halo statistics
+  DevBuf wg_word, wg_prefix, gen, halo;
+  int n_cu = 0;
+  bool use_stream = true;         // 0: always the tiled kernel (comparisons)
+  uint32_t spin = kStreamSpin;    // polls of a cross-workgroup word before giving up
+  std::vector<std::pair<uint64_t, int>> occ;  // (geometry key, workgroups per CU)
   // kernel timing: every timing-th bank launch (0: off)
   int timing = 0;
   uint64_t timing_seen = 0;
@@ -260,6 +267,18 @@ struct Pending {
 // an earlier one never does), so it can run under stream capture.
 void drop_graph(pulscan_ctx *ctx);
 
+// Workgroups of the streaming kernel resident per CU for this geometry
+// (cached per geometry).
+int stream_occ(pulscan_ctx *ctx, const StreamGeometry &g, bool from_power) {
+  const uint64_t key = ((uint64_t)g.lds_bytes << 16) | ((uint64_t)g.K << 8) |
+                       ((uint64_t)g.EPL << 1) | (from_power ? 1u : 0u);
+  for (auto &e : ctx->occ)
+    if (e.first == key) return e.second;
+  const int n = stream_occupancy(g, from_power);
+  ctx->occ.emplace_back(key, n);
+  return n;
+}
+
 int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a, Pending *pend) {
   hipStream_t stream = (hipStream_t)a.opts.stream;
   const int nspec = (int)specs.size();
@@ -274,9 +293,23 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     n_min = s.n < n_min ? s.n : n_min;
   }
   const bool fp16 = search && a.opts.power_fp16;
-  Geometry g;
-  if (!choose_geometry(a.chunk, a.block, zmax_max, n_min, &g, a.tile, fp16))
+  const bool exact = a.opts.norm == PULSCAN_NORM_EXACT;
+  // the streaming kernel serves what it can (search and tables), the tiled
+  // kernel the rest (normalisation-only passes, the exact median, FP16
+  // power, and sizes outside the streaming kernel's geometry)
+  StreamGeometry sgeo{};
+  int occ = 0;
+  const bool sk = ctx->use_stream && !power_only && a.tile == 0 &&
+                      choose_stream_geometry(a.chunk, a.block, zmax_max, a.from_power, exact,
+                                             fp16, &sgeo) &&
+                      (occ = stream_occ(ctx, sgeo, a.from_power)) > 0;
+  Geometry g{};
+  if (sk) {
+    g.K = sgeo.K;
+  } else if (!choose_geometry(a.chunk, a.block, zmax_max, n_min, &g, a.tile, fp16)) {
     return PULSCAN_EUNSUPPORTED;
+  }
+  const uint32_t sblock = sk ? 64u * (uint32_t)sgeo.EPL : 0u;
   // FP16 search on spectra: room for every block's statistics
   float *stats = nullptr;
   if (fp16 && !a.from_power) {
@@ -289,7 +322,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
 
   // descriptors
   std::vector<SpecDesc> descs(nspec);
-  uint64_t tiles = 0;
+  uint64_t tiles = 0, blocks = 0;
   uint32_t zc_max = 0;
   for (int s = 0; s < nspec; ++s) {
     SpecDesc &d = descs[s];
@@ -307,8 +340,13 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     d.dofmul = specs[s].dofmul;
     d.spec_id = specs[s].spec_id;
     d.harm = specs[s].harm;
-    d.tile_begin = tiles;
-    tiles += (specs[s].n + g.tile - 1) / g.tile;
+    if (sk) {
+      d.block_begin = blocks;
+      blocks += (specs[s].n + sblock - 1) / sblock;
+    } else {
+      d.tile_begin = tiles;
+      tiles += (specs[s].n + g.tile - 1) / g.tile;
+    }
     if (a.opts.ntrials > 0.0) {
       d.ntrials = a.opts.ntrials;
     } else {
@@ -376,7 +414,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   bp.P_out = a.P_out;
   bp.stats_out = a.stats_out;
 
-  // staging: a pool for the candidates and per-tile counts and offsets
+  // staging: a pool for the candidates and per-unit counts and offsets
   uint64_t worst = 0;
   for (const SpecDesc &d : descs) worst += (uint64_t)d.nchunks * d.zmax;
   if (worst >= (1ull << 32)) return PULSCAN_EUNSUPPORTED;
@@ -384,20 +422,35 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   const bool best = search && a.opts.best_per_chunk;
   const bool fin = best || fp16;  // a final pass compacts the emitted list
   Counters *cnt = nullptr;
-  if (search) {
-    st = grow(ctx, ctx->pool, (size_t)pool_cap * sizeof(StageEntry), false);
-    if (st) return st;
-    st = grow(ctx, ctx->tile_word, tiles * sizeof(unsigned long long), true);
-    if (st) return st;
-    st = grow(ctx, ctx->tile_prefix, (tiles + 1) * sizeof(uint32_t), false);
-    if (st) return st;
+  // the streaming kernel's workgroups: as many as are resident, each range
+  // at least a batch and the halo long
+  const uint64_t min_range = sgeo.lag > (uint32_t)kStreamBatch ? sgeo.lag : (uint64_t)kStreamBatch;
+  uint64_t nwg = 0;
+  if (sk) {
+    nwg = (uint64_t)occ * (uint64_t)ctx->n_cu;
+    const uint64_t by_size = blocks / min_range;
+    nwg = by_size < nwg ? by_size : nwg;
+    if (nwg < 1) nwg = 1;
+  }
+  if (search || sk) {
     st = grow(ctx, ctx->counters, sizeof(Counters), true);
     if (st) return st;
     cnt = static_cast<Counters *>(ctx->counters.p);
+  }
+  if (search) {
+    st = grow(ctx, ctx->pool, (size_t)pool_cap * sizeof(StageEntry), false);
+    if (st) return st;
+    if (!sk) {
+      st = grow(ctx, ctx->tile_word, tiles * sizeof(unsigned long long), true);
+      if (st) return st;
+      st = grow(ctx, ctx->tile_prefix, (tiles + 1) * sizeof(uint32_t), false);
+      if (st) return st;
+    }
     if (ctx->counts_dirty) {
       // re-arm what a failed launch left behind (never under capture: a
       // failure drops the graph, so the next call runs directly)
-      HIP_TRY(hipMemsetAsync(ctx->tile_word.p, 0, ctx->tile_word.bytes, stream));
+      if (ctx->tile_word.p)
+        HIP_TRY(hipMemsetAsync(ctx->tile_word.p, 0, ctx->tile_word.bytes, stream));
       HIP_TRY(hipMemsetAsync(&cnt->head, 0, sizeof(cnt->head), stream));
       ctx->counts_dirty = false;
     }
@@ -410,13 +463,23 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     bp.total2 = fin ? nullptr : reinterpret_cast<unsigned long long *>(a.out->count_device);
     bp.overflow = &cnt->overflow;
     bp.scan_in_kernel = tiles <= kInKernelScanMax ? 1 : 0;
-    if (!bp.scan_in_kernel) {
+    if (!sk && !bp.scan_in_kernel) {
       const uint64_t nspan = (tiles + kScanSpan - 1) / kScanSpan;
       st = grow(ctx, ctx->span_sum, nspan * sizeof(uint32_t), false);
       if (st) return st;
       st = grow(ctx, ctx->span_prefix, nspan * sizeof(uint32_t), false);
       if (st) return st;
     }
+  }
+  if (sk) {
+    st = grow(ctx, ctx->wg_word, nwg * sizeof(unsigned long long), true);
+    if (st) return st;
+    st = grow(ctx, ctx->wg_prefix, (nwg + 1) * sizeof(uint32_t), false);
+    if (st) return st;
+    st = grow(ctx, ctx->gen, sizeof(uint32_t), true);
+    if (st) return st;
+    st = grow(ctx, ctx->halo, nwg * sgeo.lag * 4 * sizeof(unsigned long long), true);
+    if (st) return st;
   }
 
   if (nspec > 1) {
@@ -444,13 +507,46 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     if (!e0 || !e1) return PULSCAN_EHIP;
     HIP_TRY(hipEventRecord(e0, stream));
   }
-  HIP_TRY(launch_bank(g, bp, tiles, stream));
+  if (sk) {
+    StreamParams sp{};
+    sp.descs = bp.descs;
+    sp.single = descs[0];
+    sp.nspec = nspec;
+    sp.total_blocks = blocks;
+    sp.align = 1;
+    sp.nwg = (uint32_t)nwg;
+    sp.chunk = a.chunk;
+    sp.block = sblock;
+    sp.zmax_max = zmax_max;
+    sp.g = sgeo;
+    sp.mode = search ? kModeSearch : kModeTables;
+    sp.dense = a.opts.dense ? 1 : 0;
+    sp.from_power = a.from_power ? 1 : 0;
+    sp.spin = ctx->spin;
+    sp.pool = bp.pool;
+    sp.pool_cap = pool_cap;
+    sp.pool_head = &cnt->head;
+    sp.wg_word = static_cast<unsigned long long *>(ctx->wg_word.p);
+    sp.wg_prefix = static_cast<uint32_t *>(ctx->wg_prefix.p);
+    sp.gen = static_cast<uint32_t *>(ctx->gen.p);
+    sp.halo = static_cast<unsigned long long *>(ctx->halo.p);
+    sp.total = &cnt->total;
+    sp.total2 = bp.total2;
+    sp.overflow = &cnt->overflow;
+    sp.M = a.M;
+    sp.I = a.I;
+    sp.P_out = a.P_out;
+    sp.stats_out = a.stats_out;
+    HIP_TRY(launch_stream(sp, stream));
+  } else {
+    HIP_TRY(launch_bank(g, bp, tiles, stream));
+  }
   if (e1) {
     HIP_TRY(hipEventRecord(e1, stream));
     ctx->ev_rec.emplace_back(e0, e1);
   }
   if (!search) return PULSCAN_OK;
-  if (!bp.scan_in_kernel) {
+  if (!sk && !bp.scan_in_kernel) {
     BigScan bs{};
     bs.tile_word = bp.tile_word;
     bs.tile_prefix = bp.tile_prefix;
@@ -487,8 +583,9 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   ep.nspec = nspec;
   ep.pool = bp.pool;
   ep.pool_cap = pool_cap;
-  ep.tile_prefix = bp.tile_prefix;
-  ep.span_prefix = bp.scan_in_kernel ? nullptr : static_cast<const uint32_t *>(ctx->span_prefix.p);
+  ep.tile_prefix = sk ? static_cast<const uint32_t *>(ctx->wg_prefix.p) : bp.tile_prefix;
+  ep.span_prefix = (sk || bp.scan_in_kernel) ? nullptr
+                                             : static_cast<const uint32_t *>(ctx->span_prefix.p);
   ep.total = bp.total;
   ep.chunk = a.chunk;
   ep.rblock = (uint32_t)a.opts.rblock;
@@ -862,7 +959,9 @@ int pulscan_ctx_create(pulscan_ctx **out, int device) {
   pulscan_ctx *ctx = new (std::nothrow) pulscan_ctx();
   if (!ctx) return PULSCAN_ENOMEM;
   ctx->device = device;
-  if (hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming) != hipSuccess ||
+  if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreate(&ctx->cap_stream) != hipSuccess) {
     (void)hipGetLastError();
     pulscan_ctx_destroy(ctx);
@@ -882,7 +981,8 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
                     &ctx->counters, &ctx->outbuf, &ctx->descs,  &ctx->jobs,
                     &ctx->allbuf, &ctx->hpow,   &ctx->hsum,     &ctx->hjobs,
                     &ctx->tune_out, &ctx->stats,  &ctx->pdescs,
-                    &ctx->span_sum, &ctx->span_prefix};
+                    &ctx->span_sum, &ctx->span_prefix, &ctx->wg_word, &ctx->wg_prefix,
+                    &ctx->gen,      &ctx->halo};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -1062,6 +1162,22 @@ int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable) {
       ctx->ev_pool.push_back(e);
     }
   }
+  return PULSCAN_OK;
+}
+
+int pulscan_ctx_set_kernel(pulscan_ctx *ctx, int kernel) {
+  if (!ctx || (kernel != PULSCAN_KERNEL_STREAM && kernel != PULSCAN_KERNEL_TILED))
+    return PULSCAN_EINVAL;
+  const bool s = kernel == PULSCAN_KERNEL_STREAM;
+  if (s != ctx->use_stream) drop_graph(ctx);
+  ctx->use_stream = s;
+  return PULSCAN_OK;
+}
+
+int pulscan_ctx_set_spin(pulscan_ctx *ctx, uint32_t polls) {
+  if (!ctx || polls < 1) return PULSCAN_EINVAL;
+  if (polls != ctx->spin) drop_graph(ctx);
+  ctx->spin = polls;
   return PULSCAN_OK;
 }
 

@@ -1039,10 +1039,12 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
         if (pos < p.pool_cap) {
           const uint32_t cl = i / zmax, w = i - cl * zmax + 1;
           StageEntry e;
-          e.tile = (uint32_t)tg;
+          e.unit = (uint32_t)tg;
+          e.rank = rank;
+          e.spec = (uint32_t)sidx;
           e.bin = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
           e.power = unord_f32((uint32_t)(key >> 32));
-          e.rank_width = (rank << kWidthBits) | (w - 1);
+          e.width = w;
           p.pool[pos] = e;
         }
         ++rank;

@@ -26,7 +26,8 @@ struct SpecDesc {
   const float *thr;       // per-width thresholds, zc entries (+inf beyond zmax)
   float *aux;             // power mode: where the normalised power goes; FP16
                           // search: the blocks' statistics (4 floats each)
-  uint64_t tile_begin;    // first global tile of this series
+  uint64_t tile_begin;    // first global tile of this series (tiled kernel)
+  uint64_t block_begin;   // first global block of this series (streaming kernel)
   double ntrials;         // Bonferroni factor
   uint32_t n;             // bins
   uint32_t zmax;          // widths 1..zmax
@@ -38,16 +39,18 @@ struct SpecDesc {
   uint32_t pad;
 };
 
-// A staged candidate.  Each tile writes its own in (chunk, width) order to a
-// contiguous run of the staging pool; its place in the canonical output is
-// the tile's exclusive prefix plus its rank within the tile.
+// A staged candidate.  Each unit of work (a tile of the tiled kernel, a
+// workgroup's range of the streaming kernel) stages its own in canonical
+// order; a candidate's place in the output is its unit's exclusive prefix
+// plus its rank within the unit.
 struct StageEntry {
-  uint32_t tile;        // global tile index
+  uint32_t unit;        // tile or workgroup index
+  uint32_t rank;        // rank within the unit
+  uint32_t spec;        // series index in the launch
   uint32_t bin;         // window start
   float power;          // boxcar power
-  uint32_t rank_width;  // rank within the tile << 12 | (width - 1)
+  uint32_t width;       // boxcar width
 };
-constexpr uint32_t kWidthBits = 12;  // zmax <= 4096
 
 enum BankMode : int {
   kModeSearch = 0,   // stage (chunk, width) maxima that reach the threshold
@@ -119,6 +122,72 @@ inline uint32_t round_widths(uint32_t zmax, int K) { return (zmax + K - 1) / K *
 
 hipError_t launch_bank(const Geometry &g, const BankParams &p, uint64_t grid, hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// The streaming bank kernel: persistent workgroups, each owning a contiguous
+// range of normalisation blocks of the launch's series (concatenated in
+// order, each series padded to a whole number of alignment units).  A
+// workgroup streams its range through an LDS ring of blocks: it normalises a
+// batch of blocks while the next batch's loads are in flight, and searches
+// the tile of blocks whose windows the ring now holds in full.
+
+constexpr int kStreamWaves = 8;                       // waves per workgroup
+constexpr int kStreamThreads = 64 * kStreamWaves;
+constexpr int kStreamBatch = kStreamWaves;            // blocks normalised per batch
+constexpr uint32_t kStreamSpin = 1u << 20;            // polls of a cross-workgroup word before giving up
+
+struct StreamGeometry {
+  int K;              // bins per lane of the bank (4 or 16)
+  int EPL;            // normalisation elements per lane: block / 64 (4 or 16)
+  uint32_t lag;       // halo blocks a tile needs beyond itself (max over the series)
+  uint32_t ring;      // blocks in the LDS ring
+  uint32_t mirror;    // group-sum entries repeated past the ring's end
+  uint32_t zc_max;    // largest zmax rounded up to K
+  uint32_t zc_pad;    // threshold floats reserved in LDS
+  uint32_t off_sg, off_ep, off_slots, off_tl, off_items;  // LDS byte offsets
+  size_t lds_bytes;
+};
+
+struct StreamParams {
+  const SpecDesc *descs;   // device table when nspec > 1
+  SpecDesc single;         // the series when nspec == 1
+  int nspec;
+  uint64_t total_blocks;   // padded blocks of the whole launch
+  uint32_t align;          // blocks per alignment unit (range boundaries)
+  uint32_t nwg;            // workgroups (= ranges)
+  uint32_t chunk;          // C
+  uint32_t block;          // normalisation block B (the streaming unit of power input)
+  uint32_t zmax_max;
+  StreamGeometry g;
+  int mode;                // kModeSearch or kModeTables
+  int dense;               // 1: evaluate every width block
+  int from_power;          // series are float power
+  uint32_t spin;           // polls of a cross-workgroup word before giving up
+  // candidate staging
+  StageEntry *pool;
+  uint32_t pool_cap;
+  uint32_t *pool_head;     // re-armed to 0 by the scan
+  unsigned long long *wg_word;   // per workgroup: (tag << 32) | candidates staged
+  uint32_t *wg_prefix;     // per workgroup exclusive prefix; [nwg] = total
+  uint32_t *gen;           // launch generation; tags are gen + 1
+  unsigned long long *halo;      // per workgroup: lag x 4 published statistics words
+  unsigned long long *total;
+  unsigned long long *total2;
+  uint32_t *overflow;      // 1: pool too small; 2: a count never arrived
+  // tables mode (series 0)
+  float *M;
+  uint32_t *I;
+  float *P_out;
+  float *stats_out;
+};
+
+// The geometry of the streaming kernel for these sizes, or false when it does
+// not serve them (the tiled kernel then runs the search).
+bool choose_stream_geometry(uint32_t chunk, uint32_t block, uint32_t zmax_max, bool from_power,
+                            bool norm_exact, bool fp16, StreamGeometry *g);
+// Workgroups resident per CU for this geometry (0 if it cannot launch).
+int stream_occupancy(const StreamGeometry &g, bool from_power);
+hipError_t launch_stream(const StreamParams &p, hipStream_t stream);
+
 // Per-width thresholds for nspec tables laid out at thr + s * zc_stride:
 // thr[s][w-1] for w <= zmax[s] (searched), +inf otherwise; debug fills
 // -FLT_MAX for every w <= zmax[s] (every maximum qualifies).
@@ -157,14 +226,14 @@ struct BigScan {
 };
 hipError_t launch_scan_big(const BigScan &s, hipStream_t stream);
 
-// Candidate f of the staging pool goes to out[tile_prefix[tile] + rank]
+// Candidate f of the staging pool goes to out[tile_prefix[unit] + rank]
 // (when that is below capacity), with its FP64 significance.
 struct EmitParams {
   const SpecDesc *descs;           // device table, or nullptr for one series
   int nspec;
   const StageEntry *pool;
   uint32_t pool_cap;
-  const uint32_t *tile_prefix;
+  const uint32_t *tile_prefix;     // per unit: exclusive prefix of the counts
   const uint32_t *span_prefix;     // non-null: tile_prefix is relative to its kScanSpan span
   const unsigned long long *total;
   uint32_t chunk;

@@ -248,22 +248,10 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
   const uint64_t lim = total < p.pool_cap ? total : p.pool_cap;
   for (uint64_t f = f0; f < lim; f += stride) {
     const StageEntry e = f == f0 ? e0 : p.pool[f];
-    const uint64_t dest = (uint64_t)p.tile_prefix[e.tile] + (e.rank_width >> kWidthBits) +
-                          (p.span_prefix ? p.span_prefix[e.tile / kScanSpan] : 0u);
-    int s = 0;
-    if (p.nspec > 1) {
-      int a = 0, b = p.nspec - 1;
-      while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (p.descs[mid].tile_begin <= e.tile)
-          a = mid;
-        else
-          b = mid - 1;
-      }
-      s = a;
-    }
-    const SpecDesc &d = p.nspec > 1 ? p.descs[s] : single;
-    const uint32_t w = (e.rank_width & ((1u << kWidthBits) - 1u)) + 1u;
+    const uint64_t dest = (uint64_t)p.tile_prefix[e.unit] + e.rank +
+                          (p.span_prefix ? p.span_prefix[e.unit / kScanSpan] : 0u);
+    const SpecDesc &d = p.nspec > 1 ? p.descs[e.spec] : single;
+    const uint32_t w = e.width;
     double lp = log_sf_chi2_even((double)e.power, w * d.dofmul) + log(d.ntrials);
     float pw = e.power;
     bool recheck = false;

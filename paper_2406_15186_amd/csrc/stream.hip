@@ -1,0 +1,1163 @@
+// The streaming bank kernel: one persistent workgroup per contiguous range of
+// normalisation blocks does normalisation, power, the boxcar bank of every
+// width, the per-chunk maxima with the threshold test and the staging of the
+// candidates, reading every bin of its range from HBM once.
+//
+//  * Streaming.  A workgroup's range (a run of blocks of one or more series)
+//    is taken a batch of kStreamBatch blocks at a time, one block per wave.
+//    The next batch's loads are in flight (in registers) while the current
+//    one is normalised and searched, so the HBM stream never waits for the
+//    search.  Normalised power goes to an LDS ring of blocks; a tile of
+//    blocks is searched once the ring holds every bin its windows reach
+//    (zmax - 1 bins past its end, `lag` blocks).
+//  * Halo.  The windows of a range's last tile reach into the next range,
+//    which another workgroup normalises.  That workgroup publishes the four
+//    statistics of its first `lag` blocks as soon as it has them; the
+//    neighbour then reads only the bins its windows need and normalises them
+//    with those statistics (the same arithmetic, so the same bits).  A word
+//    that does not arrive in time is recomputed from the block itself.
+//  * Normalisation (section 2.2.3; section 2.5 and the appendix algorithm
+//    "Median of Medians Normalisation"): lane l of a wave holds elements
+//    l + 64m of its block, so the first levels of the median-of-4 tree stay
+//    in the lane and the last three cross lanes.  The cross-lane levels of
+//    the real and imaginary trees run through one set of lane permutations
+//    and DPP min/max operations.
+//  * Bank (section 2.2.5, appendix algorithm "Boxcar Filtering Process"): as
+//    in the tiled kernel, a per-lane upper bound on K starts' windows finds
+//    the first width block that might reach a threshold, and flagged lanes
+//    are evaluated exactly by the whole workgroup, in a canonical FP32 order
+//    (eval_unit) shared with the dense route.
+//  * Staging: each tile's (chunk, width) maxima that reach their thresholds
+//    are staged in order with their rank in the workgroup's range; the last
+//    workgroup scans the ranges' counts.
+//
+// This translation unit is built without NaN semantics (inputs are finite;
+// bins past a series' end are -inf), which lets the compiler fold the
+// cross-lane moves into DPP min/max instructions.
+#include <float.h>
+
+#include "internal.hpp"
+
+namespace pulscan {
+
+#define GAS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GAS T *gp(T *p) {
+  return (GAS T *)p;
+}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Row pitch (floats) of a ring segment of 64 K-bin groups: the 64 lane
+// columns plus 64/K pad words, so that 64 lanes reading "their" j-th bin and
+// the normalising wave's writes both fall on distinct banks (or two-way).
+template <int K>
+__host__ __device__ constexpr int spitch() {
+  return 64 + 64 / K;
+}
+// Starts one exact-pass unit evaluates together (four: the unit's working
+// set stays small beside the batch of loads in flight).
+template <int K>
+__host__ __device__ constexpr int sks() {
+  return K < 4 ? K : 4;
+}
+// Width blocks per step of the bound.
+constexpr int kSBoundBatch = 8;
+// Safety factor of the pruning bound (see the tiled kernel): a union sum of
+// non-negative FP32 terms compared with T (1 - 2^-10) never skips a window
+// whose FP32 boxcar reaches T, for zmax <= 4096.
+constexpr float kSBoundSlack = 1.0f - 1.0f / 1024.0f;
+
+// ---------------------------------------------------------------------------
+// Median of medians
+
+// Twice the median of four values (the sum of the middle two; see the tiled
+// kernel): five VALU operations.
+__device__ __forceinline__ float m4x2(float a, float b, float c, float d) {
+  const float m = __builtin_amdgcn_fmed3f(a, b, c);
+  const float lo = fminf(fminf(a, b), c), hi = fmaxf(fmaxf(a, b), c);
+  return m + __builtin_amdgcn_fmed3f(lo, d, hi);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float sdpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// Inside each row of 16 lanes, lane l (for the lanes used) receives twice the
+// median of x[l], x[l+S], x[l+2S], x[l+3S], as max(min(a, b), min(c, d)) +
+// min(max(a, b), max(c, d)): the same two middle values as m4x2, so the same
+// bits.  The row shifts fold into the min/max instructions.
+template <int S>
+__device__ __forceinline__ float row_m4x2(float x) {
+  constexpr int C1 = 0x100 + S, C2 = 0x100 + 2 * S;
+  const float lo = fminf(x, sdpp<C1>(x)), hi = fmaxf(x, sdpp<C1>(x));
+  return fmaxf(lo, sdpp<C2>(lo)) + fminf(hi, sdpp<C2>(hi));
+}
+
+// The three cross-lane levels of two trees at once.  x holds tree A's 64
+// values, y tree B's; the level over lanes l, l+16, l+32, l+48 regroups the
+// values so that row 0 holds tree A's pairs (l, l+16) and row 1 its pairs
+// (l+32, l+48), rows 2 and 3 tree B's, and finishes with one exchange of
+// rows; the next two levels then run on rows 0 and 2 together.  Returns the
+// wave-uniform results (each doubled at every level).
+__device__ __forceinline__ void cross2(float x, float y, uint32_t lane, float &ra, float &rb) {
+  const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                   false);
+  // rows: [A0-15, A16-31, B0-15, B16-31] and [A32-47, A48-63, B32-47, B48-63]
+  const auto s2 = __builtin_amdgcn_permlane16_swap(s1[0], s1[1], false, false);
+  // rows: [A0-15, A32-47, B0-15, B32-47] and [A16-31, A48-63, B16-31, B48-63]
+  const float p = __uint_as_float(s2[0]), q = __uint_as_float(s2[1]);
+  const float lo = fminf(p, q), hi = fmaxf(p, q);
+  const auto s3 = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false,
+                                                   false);
+  // even rows: own low and the odd row's low; odd rows: the even row's high
+  // and own high
+  const float u = __uint_as_float(s3[0]), v = __uint_as_float(s3[1]);
+  const float z = (lane & 16) ? fminf(u, v) : fmaxf(u, v);
+  const auto s4 = __builtin_amdgcn_permlane16_swap(__float_as_uint(z), __float_as_uint(z), false,
+                                                   false);
+  float w = z + __uint_as_float(s4[1]);
+  w = row_m4x2<4>(w);
+  w = row_m4x2<1>(w);
+  ra = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w), 0));
+  rb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w), 32));
+}
+
+// The in-lane levels of one tree over the lane's EPL values (or their
+// magnitudes), doubled at each level.
+template <int EPL, bool ABS>
+__device__ __forceinline__ float lane_tree(const float (&v)[EPL]) {
+  auto f = [](float x) { return ABS ? fabsf(x) : x; };
+  if constexpr (EPL == 4) {
+    return m4x2(f(v[0]), f(v[1]), f(v[2]), f(v[3]));
+  } else {
+    float t[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) t[m] = m4x2(f(v[m]), f(v[m + 4]), f(v[m + 8]), f(v[m + 12]));
+    return m4x2(t[0], t[1], t[2], t[3]);
+  }
+}
+
+struct BlockStats {
+  float med_re, mad_re, med_im, mad_im;
+};
+
+// Median-of-medians statistics of a block held as re[m], im[m] = element
+// lane + 64m; re and im become the deviations from their medians.
+template <int EPL>
+__device__ __forceinline__ BlockStats block_stats(float (&re)[EPL], float (&im)[EPL], uint32_t lane) {
+  // log4(EPL) in-lane levels and three cross-lane levels, each doubling
+  constexpr float scale = EPL == 16 ? 1.0f / 32.0f : 1.0f / 16.0f;
+  BlockStats s;
+  float a, b;
+  cross2(lane_tree<EPL, false>(re), lane_tree<EPL, false>(im), lane, a, b);
+  s.med_re = a * scale;
+  s.med_im = b * scale;
+#pragma unroll
+  for (int m = 0; m < EPL; ++m) {
+    re[m] -= s.med_re;
+    im[m] -= s.med_im;
+  }
+  cross2(lane_tree<EPL, true>(re), lane_tree<EPL, true>(im), lane, a, b);
+  s.mad_re = a * scale;
+  s.mad_im = b * scale;
+  return s;
+}
+
+// Normalised power of a deviation pair (section 2.2.3): each component
+// divided by its block's scaled MAD (0 when the MAD is 0), squared, summed.
+struct Scales {
+  float re, im;
+};
+__device__ __forceinline__ Scales scales_of(const BlockStats &s) {
+  Scales c;
+  c.re = s.mad_re > 0.f ? 1.0f / (s.mad_re * kMadScale) : 0.f;
+  c.im = s.mad_im > 0.f ? 1.0f / (s.mad_im * kMadScale) : 0.f;
+  return c;
+}
+__device__ __forceinline__ float power_of(float dre, float dim, const Scales &c) {
+  const float a = dre * c.re, b = dim * c.im;
+  return fmaf(a, a, b * b);
+}
+
+// Order-preserving map of a float to 32 bits and back.
+__device__ __forceinline__ uint32_t sord(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float sunord(uint32_t o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+// threadIdx.x through an empty asm statement, so that each phase recomputes
+// its lane addresses instead of keeping them live across the kernel.
+__device__ __forceinline__ uint32_t ftid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// LDS views
+
+template <int K>
+struct Ring {
+  float *P;          // power ring: segments of 64 groups x K bins, lane-major
+  float *Sg;         // group sums, per ring group position (+ mirror)
+  float *E[3];       // first-group partial sums E(3), E(7), E(15) (+ mirror)
+  uint32_t NG;       // groups in the ring
+  uint32_t mirror;   // entries repeated past NG
+  // power address of bin j of the group at ring position q
+  __device__ __forceinline__ float *bin(uint32_t q, uint32_t j) const {
+    return P + (q >> 6) * (K * spitch<K>()) + j * spitch<K>() + (q & 63);
+  }
+  __device__ __forceinline__ uint32_t wrap(uint32_t q) const { return q >= NG ? q - NG : q; }
+};
+
+// Group sums of the groups [gi0, gi1) of the block at ring slot `slot`
+// (block-relative group indices), each summed from zero in increasing order,
+// and the partial sums over their first 3, 7 and 15 bins (the first width
+// block's bound).  CLAMP counts -inf (past a series' end) as 0.
+template <int K, int EPL, bool CLAMP>
+__device__ __forceinline__ void group_sums(const Ring<K> &R, uint32_t slot, uint32_t gi1,
+                                           uint32_t lane) {
+  constexpr uint32_t GPB = 64 * EPL / K;
+  for (uint32_t gi = lane; gi < gi1; gi += 64) {
+    const uint32_t q = slot * GPB + gi;
+    const float *c = R.bin(q, 0);
+    float e = 0.f, e3 = 0.f, e7 = 0.f, e15 = 0.f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      float v = c[j * spitch<K>()];
+      if (CLAMP) v = fmaxf(v, 0.f);
+      e = j == 0 ? v : e + v;
+      if (j == 2) e3 = e;
+      if (j == 6) e7 = e;
+      if (j == 14) e15 = e;
+    }
+    R.Sg[q] = e;
+    R.E[0][q] = e3;
+    if (K >= 8) R.E[1][q] = e7;
+    if (K >= 16) R.E[2][q] = e15;
+    if (q < R.mirror) {
+      R.Sg[q + R.NG] = e;
+      R.E[0][q + R.NG] = e3;
+      if (K >= 8) R.E[1][q + R.NG] = e7;
+      if (K >= 16) R.E[2][q + R.NG] = e15;
+    }
+  }
+}
+
+// A block's ring slot with no spectrum behind it (past the series' end): the
+// first `need` bins are -inf, their groups' sums 0.
+template <int K, int EPL>
+__device__ __forceinline__ void fill_past_end(const Ring<K> &R, uint32_t slot, uint32_t need,
+                                              uint32_t lane) {
+  constexpr uint32_t GPB = 64 * EPL / K;
+  for (uint32_t r = lane; r < need; r += 64) {
+    const uint32_t q = slot * GPB + r / K;
+    *R.bin(q, r % K) = -INFINITY;
+  }
+  for (uint32_t gi = lane; gi < need / K; gi += 64) {
+    const uint32_t q = slot * GPB + gi;
+    R.Sg[q] = 0.f;
+#pragma unroll
+    for (int k = 0; k < (K >= 16 ? 3 : K >= 8 ? 2 : 1); ++k) R.E[k][q] = 0.f;
+    if (q < R.mirror) {
+      R.Sg[q + R.NG] = 0.f;
+#pragma unroll
+      for (int k = 0; k < (K >= 16 ? 3 : K >= 8 ? 2 : 1); ++k) R.E[k][q + R.NG] = 0.f;
+    }
+  }
+}
+
+__device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// ---------------------------------------------------------------------------
+// Loads.  A block's raw data: lane l element m is bin s0 + l + 64m of the
+// block's statistics window (the block, or the series' last B bins for a
+// partial last block).  Power input: the block's own bins.
+
+// What the kernel needs of a series descriptor, held by value.
+struct Series {
+  const float2 *x;
+  const float *thr;
+  uint64_t block_begin;
+  uint32_t n, zmax, zc;
+};
+
+template <int EPL, bool FP>
+struct Raw {
+  f32x2 v[FP ? (EPL + 1) / 2 : EPL];  // power input packs two elements per slot
+};
+
+// A wave-uniform value passed through an empty asm statement, so that what
+// is derived from it (load addresses, per-element conditions) is computed
+// where it is used rather than hoisted out of the loop and kept live.
+__device__ __forceinline__ uint32_t fresh_u(uint32_t v) {
+  v = __builtin_amdgcn_readfirstlane(v);
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// Loads of a block: unconditional, from one base address with immediate
+// offsets, so that they stay in flight without branches around them.  A
+// spectrum block reads its statistics window (the block, or the series' last
+// B bins for a partial last block); a power block reads its own bins, indices
+// clamped into the series for a partial last block (those values are never
+// used).
+template <int EPL, bool FP>
+__device__ __forceinline__ void load_block(const Series &d, uint32_t k, Raw<EPL, FP> &r) {
+  constexpr uint32_t B = 64 * EPL;
+  const uint32_t lane = ftid() & 63;
+  const uint32_t own = fresh_u(k * B), n = d.n;
+  if constexpr (FP) {
+    const GAS float *x = gp(reinterpret_cast<const float *>(d.x));
+    if (own + B <= n) {
+      const GAS float *xl = x + own + lane;
+#pragma unroll
+      for (int m = 0; m < EPL; ++m) {
+        const float v = xl[64 * m];
+        if (m & 1)
+          r.v[m / 2].y = v;
+        else
+          r.v[m / 2].x = v;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < EPL; ++m) {
+        const float v = x[min(own + lane + 64 * m, n - 1)];
+        if (m & 1)
+          r.v[m / 2].y = v;
+        else
+          r.v[m / 2].x = v;
+      }
+    }
+  } else {
+    const uint32_t s0 = own + B > n ? n - B : own;
+    const GAS f32x2 *xl = gp(reinterpret_cast<const f32x2 *>(d.x)) + s0 + lane;
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) r.v[m] = xl[64 * m];
+  }
+}
+
+// The first `need` bins of block k (need a multiple of 64): a halo block
+// normalised with published statistics.  The series' partial last block is
+// loaded whole (its statistics window), as the normalisation expects.
+template <int EPL, bool FP>
+__device__ __forceinline__ void load_prefix(const Series &d, uint32_t k, uint32_t need,
+                                            Raw<EPL, FP> &r) {
+  constexpr uint32_t B = 64 * EPL;
+  const uint32_t own = fresh_u(k * B), nd = fresh_u(need);
+  if (own + B > d.n) {
+    load_block<EPL, FP>(d, k, r);
+    return;
+  }
+  const uint32_t lane = ftid() & 63;
+#pragma unroll
+  for (int m = 0; m < EPL; ++m) {
+    if (64u * m < nd) {  // uniform
+      if constexpr (FP) {
+        const float v = gp(reinterpret_cast<const float *>(d.x))[own + lane + 64 * m];
+        if (m & 1)
+          r.v[m / 2].y = v;
+        else
+          r.v[m / 2].x = v;
+      } else {
+        r.v[m] = gp(reinterpret_cast<const f32x2 *>(d.x))[own + lane + 64 * m];
+      }
+    }
+  }
+}
+
+// Where a block's normalisation results go besides the ring.
+struct NormOut {
+  float *P_out;       // tables mode: the normalised power (series bins)
+  float *stats_out;   // tables mode: 4 floats per block
+  unsigned long long *pub;  // non-null: publish the statistics (4 tagged words)
+  uint32_t tag;
+};
+
+// Normalise block k of series d (raw data in r, loaded by load_block) or, with
+// `given`, only its first `limit` bins with the given statistics (raw data
+// from load_prefix); write the power of bins [0, limit) of the block into ring
+// slot `slot`, -inf for bins past the series' end, and the block's group
+// sums.  One whole wave.
+template <int K, int EPL, bool FP>
+__device__ __forceinline__ void normalise(const Series &d, uint32_t k, Raw<EPL, FP> &r,
+                                          bool use_given, const BlockStats &given, uint32_t limit,
+                                          const Ring<K> &R, uint32_t slot, const NormOut &o,
+                                          uint32_t lane) {
+  constexpr uint32_t B = 64 * EPL, SEG = 64 * K, GPB = B / K;
+  constexpr int PITCH = spitch<K>();
+  const uint32_t own = k * B, n = d.n;
+  const bool partial = own + B > n;           // the series' last block, not whole
+  const uint32_t s0 = (!FP && partial) ? n - B : own;
+  float *base = R.P + slot * (B / SEG) * (K * PITCH);
+  float P[EPL];
+  if constexpr (FP) {
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) P[m] = (m & 1) ? r.v[m / 2].y : r.v[m / 2].x;
+  } else {
+    float re[EPL], im[EPL];
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) {
+      re[m] = r.v[m].x;
+      im[m] = r.v[m].y;
+    }
+    BlockStats st;
+    if (use_given) {
+      st = given;
+#pragma unroll
+      for (int m = 0; m < EPL; ++m) {
+        re[m] -= st.med_re;
+        im[m] -= st.med_im;
+      }
+    } else {
+      st = block_stats<EPL>(re, im, lane);
+      if (o.pub && lane < 4) {
+        const float v = lane == 0 ? st.med_re : lane == 1 ? st.mad_re : lane == 2 ? st.med_im : st.mad_im;
+        __hip_atomic_store(o.pub + lane, ((unsigned long long)o.tag << 32) | __float_as_uint(v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (o.stats_out && lane == 0) {
+        GAS float *so = gp(o.stats_out) + 4 * (size_t)k;
+        so[0] = st.med_re;
+        so[1] = st.mad_re;
+        so[2] = st.med_im;
+        so[3] = st.mad_im;
+      }
+    }
+    const Scales c = scales_of(st);
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) P[m] = power_of(re[m], im[m], c);
+  }
+  if (!partial && s0 == own && limit == B) {
+    // a whole block: lane l element m is block bin l + 64m, at row l % K,
+    // column l / K + (64/K)(m % K) of segment m / K
+    float *lb = base + (lane % K) * PITCH + lane / K;
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) lb[(m / K) * (K * PITCH) + (64 / K) * (m % K)] = P[m];
+    if (o.P_out) {
+#pragma unroll
+      for (int m = 0; m < EPL; ++m) gp(o.P_out)[own + lane + 64 * m] = P[m];
+    }
+    lds_wait();
+    group_sums<K, EPL, false>(R, slot, GPB, lane);
+  } else {
+    // a partial block, or the first bins of a halo block (rare): addresses
+    // from fresh copies of the lane id and the bounds, so that the compiler
+    // does not hoist them into the streaming loop
+    const uint32_t ln = ftid() & 63, s0f = fresh_u(s0), ownf = fresh_u(own);
+    const uint32_t lim = fresh_u(limit), nf = fresh_u(n);
+    float *const bf = R.P + fresh_u(slot * (B / SEG) * (K * PITCH));
+#pragma unroll
+    for (int m = 0; m < EPL; ++m) {
+      const uint32_t t = s0f + ln + 64 * m;
+      if (t >= ownf && t - ownf < lim) {
+        const uint32_t rr = t - ownf, sg = rr / SEG, rs = rr % SEG;
+        bf[sg * (K * PITCH) + (rs % K) * PITCH + rs / K] = t < nf ? P[m] : -INFINITY;
+        if (o.P_out && t < nf) gp(o.P_out)[t] = P[m];
+      }
+    }
+    // bins past the end that no element covered
+    for (uint32_t rr = (nf > ownf ? nf - ownf : 0) + ln; rr < lim; rr += 64) {
+      const uint32_t sg = rr / SEG, rs = rr % SEG;
+      bf[sg * (K * PITCH) + (rs % K) * PITCH + rs / K] = -INFINITY;
+    }
+    lds_wait();
+    if (partial)
+      group_sums<K, EPL, true>(R, slot, limit / K, lane);
+    else
+      group_sums<K, EPL, false>(R, slot, limit / K, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The bank
+
+// First width block in which one of lane L's windows might reach its
+// threshold, or nblk if none can (powers are non-negative and thresholds
+// rise with the width, so the lane's union window bounds every window of
+// width <= (b+1) K from its K starts).  The first block is checked every few
+// widths from the lane's group sum plus the next group's partial sums.
+template <int K>
+__device__ __forceinline__ uint32_t sbound(const Ring<K> &R, uint32_t q, const float *Tb1,
+                                           const float *Tb, uint32_t nblk) {
+  const float own = R.Sg[q];
+  bool hit = own + R.E[0][q + 1] >= Tb1[0];
+  if (K >= 8) hit |= own + R.E[1][q + 1] >= Tb1[1];
+  if (K >= 16) hit |= own + R.E[2][q + 1] >= Tb1[2];
+  float U = own + R.Sg[q + 1];
+  bool later = false;
+  for (uint32_t b = 1; b < nblk; b += kSBoundBatch) {
+    float sg[kSBoundBatch], tb[kSBoundBatch];
+#pragma unroll
+    for (int k = 0; k < kSBoundBatch; ++k) {
+      const uint32_t bb = min(b + k, nblk - 1);
+      sg[k] = R.Sg[q + bb + 1];
+      tb[k] = Tb[bb];
+    }
+#pragma unroll
+    for (int k = 0; k < kSBoundBatch; ++k) {
+      if (b + k < nblk) {
+        U += sg[k];
+        later |= U >= tb[k];
+      }
+    }
+  }
+  if (hit) return 0u;
+  if (!later) return nblk;
+  // rare: find the first block that passes
+  U = own + R.Sg[q + 1];
+  for (uint32_t b = 1; b < nblk; ++b) {
+    U += R.Sg[q + b + 1];
+    if (U >= Tb[b]) return b;
+  }
+  return nblk;
+}
+
+// Exact evaluation of width block b (widths bK+1 .. bK+K) for starts
+// K0 .. K0+KS-1 of the lane whose group is at ring position q (series bin
+// bin0 = its first start), merging each width's maximum that reaches its
+// threshold into the chunk's slot (larger power wins, then the smaller bin).
+//
+// Canonical FP32 order of a boxcar.  With the lane's K starts s and the
+// window [s, s + w) ending at position p = s + w - 1 of the lane's groups:
+//   * p < K (inside the lane's own group): the bins s..p summed from zero in
+//     increasing order;
+//   * otherwise, with the window ending in group g = p / K >= 1 at its
+//     e = p % K + 1-th bin:  Y = (H_s + G_g) + E_g(e),  where H_s sums the
+//     own group's bins K-1 down to s from zero, G_g sums the group sums of
+//     groups 1 .. g-1 from zero in increasing order (G_1 = 0, H_s + 0 = H_s),
+//     and E_g(e) sums group g's first e bins from zero in increasing order.
+// Both the dense and the pruned routes use this order (the dense route is
+// this function applied to every unit), so they agree bit for bit; any width
+// block can be entered from the group sums alone.  (Sums of non-negative
+// terms: every order is within (w - 1) u of the exact sum.)
+template <int K, int K0>
+__device__ __forceinline__ void eval_unit(const Ring<K> &R, uint32_t q, uint32_t b,
+                                          const float *Tl, uint32_t zmax,
+                                          unsigned long long *slot_row, uint32_t bin0) {
+  constexpr int KS = sks<K>();
+  constexpr int PITCH = spitch<K>();
+  // the lane's own bins K0 .. K-1 and H_s for s = K0 .. K0+KS-1
+  const float *po = R.bin(q, 0);
+  float own[K - K0];
+#pragma unroll
+  for (int j = K0; j < K; ++j) own[j - K0] = po[j * PITCH];
+  float H[KS];
+  {
+    float h = 0.f;
+#pragma unroll
+    for (int j = K - 1; j >= K0; --j) {
+      h = j == K - 1 ? own[j - K0] : h + own[j - K0];
+      if (j < K0 + KS) H[j - K0] = h;
+    }
+  }
+  // prefix sums of the group after the window-end group's (EB: e = 1 .. K0+KS-1)
+  constexpr int NB1 = K0 + KS - 1;
+  float EB[NB1 > 0 ? NB1 : 1];
+  {
+    const float *pb = R.bin(R.wrap(q + b + 1), 0);
+#pragma unroll
+    for (int j = 0; j < NB1; ++j) {
+      const float v = pb[j * PITCH];
+      EB[j] = j == 0 ? v : EB[j - 1] + v;
+    }
+  }
+  // each width's maximum over the KS starts, merged into the slot when it
+  // reaches the width's threshold (first start attaining it)
+  auto merge = [&](int u, const float (&y)[KS]) __attribute__((always_inline)) {
+    float m = y[0];
+#pragma unroll
+    for (int k = 1; k < KS; ++k) m = fmaxf(m, y[k]);
+    const uint32_t wi = b * K + u;
+    if (m >= Tl[wi] && wi < zmax) {
+      uint32_t kk = KS - 1;
+#pragma unroll
+      for (int k = KS - 2; k >= 0; --k) kk = y[k] == m ? (uint32_t)k : kk;
+      const unsigned long long key =
+          ((unsigned long long)sord(m) << 32) | (0xFFFFFFFFu - (bin0 + K0 + kk));
+      atomicMax(&slot_row[wi], key);
+    }
+  };
+  if (b == 0) {
+    // in-group windows by the recursion; crossing ones from H_s
+    float t[KS];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      float y[KS];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int s = K0 + k;
+        if (s + u < K) {
+          t[k] = u == 0 ? own[s - K0] : t[k] + own[s + u - K0];
+          y[k] = t[k];
+        } else {
+          y[k] = H[k] + EB[s + u - K];
+        }
+      }
+      merge(u, y);
+    }
+  } else {
+    float G = 0.f;
+    for (uint32_t j = 1; j < b; ++j) G = j == 1 ? R.Sg[q + 1] : G + R.Sg[q + j];
+    const float G1 = b == 1 ? R.Sg[q + 1] : G + R.Sg[q + b];
+    float hA[KS], hB[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      hA[k] = b == 1 ? H[k] : H[k] + G;
+      hB[k] = H[k] + G1;
+    }
+    float EA[K];
+    {
+      const float *pa = R.bin(R.wrap(q + b), 0);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float v = pa[j * PITCH];
+        EA[j] = j == 0 ? v : EA[j - 1] + v;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      float y[KS];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int s = K0 + k;
+        y[k] = s + u < K ? hA[k] + EA[s + u] : hB[k] + EB[s + u - K];
+      }
+      merge(u, y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The kernel
+
+struct Shared {
+  uint32_t items[3];  // flagged lanes of a tile (tile t counts in items[t % 3])
+  uint32_t lost;
+  uint32_t base;
+  uint32_t wsum[kStreamWaves];
+};
+
+__device__ __forceinline__ Series series_at(const SpecDesc *descs, int s) {
+  static_assert(sizeof(SpecDesc) % 8 == 0, "descriptor of whole words");
+  constexpr int W = sizeof(SpecDesc) / 8;
+  const GAS unsigned long long *g = gp(reinterpret_cast<const unsigned long long *>(descs + s));
+  unsigned long long w[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) w[k] = g[k];
+  SpecDesc d;
+  __builtin_memcpy(&d, w, sizeof d);
+  return Series{d.x, d.thr, d.block_begin, d.n, d.zmax, d.zc};
+}
+
+// Four waves per SIMD (two workgroups per CU): at most 128 registers.
+template <int K, int EPL, bool FP>
+__global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams p) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ Shared sh;
+  constexpr uint32_t B = 64 * EPL, GPB = B / K;
+  constexpr uint32_t NB = kStreamBatch;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const uint32_t nthr = kStreamThreads;
+  // the launch's parameters as values (a reference to the argument, captured
+  // by the lambdas below, would make the compiler copy it to scratch memory)
+  const SpecDesc *descs = p.descs;
+  const int nspec = p.nspec;
+  const uint32_t nwg = p.nwg, C = p.chunk, spin = p.spin, pool_cap = p.pool_cap;
+  const uint32_t RB = p.g.ring, lag = p.g.lag;
+  StageEntry *const pool = p.pool;
+  uint32_t *const pool_head = p.pool_head;
+  unsigned long long *const halo = p.halo;
+  float *const M_out = p.M;
+  uint32_t *const I_out = p.I;
+  Ring<K> R;
+  R.P = reinterpret_cast<float *>(lds);
+  R.Sg = reinterpret_cast<float *>(lds + p.g.off_sg);
+  R.NG = RB * GPB;
+  R.mirror = p.g.mirror;
+  {
+    const uint32_t stride = R.NG + p.g.mirror;
+    float *e = reinterpret_cast<float *>(lds + p.g.off_ep);
+    R.E[0] = e;
+    R.E[1] = e + stride;
+    R.E[2] = e + 2 * stride;
+  }
+  unsigned long long *slots = reinterpret_cast<unsigned long long *>(lds + p.g.off_slots);
+  float *Tl = reinterpret_cast<float *>(lds + p.g.off_tl);
+  float *Tb1 = Tl + p.g.zc_pad;
+  float *Tb = Tb1 + 4;
+  uint32_t *items = reinterpret_cast<uint32_t *>(lds + p.g.off_items);
+
+  const uint32_t wg = blockIdx.x;
+  const uint32_t tag = *gp(p.gen) + 1u;
+  const uint64_t units = p.total_blocks / p.align;
+  const uint64_t g0 = units * wg / nwg * p.align, g1 = units * (wg + 1) / nwg * p.align;
+  const bool search = p.mode == kModeSearch;
+  const bool prune = search && !p.dense;
+  NormOut no{};
+  no.P_out = p.mode == kModeTables ? p.P_out : nullptr;
+  no.stats_out = p.mode == kModeTables ? p.stats_out : nullptr;
+  uint32_t wg_count = 0;  // candidates staged so far by this workgroup (uniform)
+  uint32_t tc = 0;        // tiles banked so far (uniform)
+  if (threadIdx.x == 0) {
+    sh.items[0] = 0u;
+    sh.items[1] = 0u;
+    sh.items[2] = 0u;
+  }
+
+  // the series holding block g0
+  int s = 0;
+  if (nspec > 1) {
+    int lo = 0, hi = nspec - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gp(descs)[mid].block_begin <= g0)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    s = lo;
+  }
+  uint64_t gc = g0;
+  while (gc < g1 && s < nspec) {
+    const Series d = nspec == 1 ? Series{p.single.x, p.single.thr, p.single.block_begin,
+                                         p.single.n, p.single.zmax, p.single.zc}
+                                : series_at(descs, s);
+    const uint32_t nbs = (d.n + B - 1) / B;
+    if (gc < d.block_begin) gc = d.block_begin;
+    if (gc >= g1) break;
+    if (gc >= d.block_begin + nbs) {  // padding after the series
+      ++s;
+      continue;
+    }
+    const uint32_t a = (uint32_t)(gc - d.block_begin);
+    const uint32_t b = (uint32_t)min(g1 - d.block_begin, (uint64_t)nbs);
+    const uint32_t n = d.n, zmax = d.zmax, zc = d.zc, nblk = zc / K;
+    const uint32_t lgs = (zc + B - 1) / B;       // halo blocks of this series
+    const bool publish = a > 0 && gc == g0;      // the previous range needs our first blocks
+    const bool consume = b < nbs;                // our last tile reaches into the next range
+    const uint32_t zpub = min(lgs, b - a);
+
+    // thresholds of the series, and the bound's minima of them
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < zc; i += nthr) Tl[i] = gp(d.thr)[i];
+    __syncthreads();
+    {
+      // the first block's sub-ranges, widths 1..4, 5..8, 9..16 (those that
+      // exist), and every width block
+      const uint32_t tid = ftid();
+      if (tid == 0) {
+        float m0 = Tl[0], m1 = INFINITY, m2 = INFINITY;
+#pragma unroll
+        for (int w = 1; w < K; ++w) {
+          if (w < 4) m0 = fminf(m0, Tl[w]);
+          else if (w < 8) m1 = fminf(m1, Tl[w]);
+          else m2 = fminf(m2, Tl[w]);
+        }
+        Tb1[0] = m0 * kSBoundSlack;
+        Tb1[1] = m1 * kSBoundSlack;
+        Tb1[2] = m2 * kSBoundSlack;
+      }
+      for (uint32_t i = tid; i < nblk; i += nthr) {
+        float m = Tl[i * K];
+#pragma unroll
+        for (int u = 1; u < K; ++u) m = fminf(m, Tl[i * K + u]);
+        Tb[i] = m * kSBoundSlack;
+      }
+    }
+
+    // the halo's statistics words, published by the next range's workgroup
+    const unsigned long long *hw = halo + (size_t)(wg + 1) * lag * 4;
+    unsigned long long *pw = halo + (size_t)wg * lag * 4;
+
+    const uint32_t nbat = (b - a + NB - 1) / NB;
+    Raw<EPL, FP> cur, nxt;
+    // issue the loads of batch j into r: block a + jNB + wave, or, for
+    // j == nbat, the halo block b + wave's first bins
+    auto issue = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
+      // r's previous contents are dead on every path (so that the compiler
+      // does not keep them alive beside the set in flight)
+      r = Raw<EPL, FP>{};
+      if (j < nbat) {
+        const uint32_t k = a + j * NB + wave;
+        if (k < b) load_block<EPL, FP>(d, k, r);
+      } else if (j == nbat && consume && wave < lgs && b + wave < nbs) {
+        const uint32_t need = min(B, (zc - wave * B + 63) / 64 * 64);
+        load_prefix<EPL, FP>(d, b + wave, need, r);
+      }
+    };
+    issue(0, cur);
+    issue(1, nxt);
+
+    uint32_t banked = a;
+    no.tag = tag;
+
+    // bank the tile of blocks [t0, t1)
+    auto bank_tile = [&](uint32_t t0, uint32_t t1) __attribute__((always_inline)) {
+      const uint32_t tb0 = t0 * B;
+      const uint32_t tbins = min((t1 - t0) * B, n - tb0);   // window starts
+      const uint32_t nlane = (tbins + K - 1) / K;            // lanes with starts
+      const uint32_t gb = ((t0 - a) % RB) * GPB;             // ring position of the tile's group 0
+      const uint32_t nch = (tbins + C - 1) / C, chunk0 = tb0 / C;
+      const uint32_t nsl = nch * zmax;
+      const uint32_t nbw = (zmax + K - 1) / K;               // width blocks
+      // tile tc counts its flagged lanes in items[tc % 3].  After its first
+      // barrier every thread has read tile tc-1's count, and no thread can
+      // reach tile tc+2's counting before passing tile tc+1's first barrier,
+      // which thread 0 reaches only after clearing items[(tc+2) % 3] here
+      const uint32_t ci = tc % 3;
+      uint32_t *cnt = &sh.items[ci];
+      ++tc;
+      if (prune) {
+        const uint32_t tid = ftid(), ln = tid & 63, wv = tid >> 6;
+        for (uint32_t sg = wv; sg * 64 < nlane; sg += kStreamWaves) {
+          const uint32_t L = sg * 64 + ln;
+          const uint32_t fl = L < nlane ? sbound<K>(R, R.wrap(gb + L), Tb1, Tb, nblk) : nblk;
+          const unsigned long long mask = __ballot(fl < nblk);
+          if (mask) {
+            uint32_t base = 0;
+            if (ln == 0) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+            base = __shfl(base, 0, 64);
+            if (fl < nblk) items[base + __popcll(mask & ((1ull << ln) - 1ull))] = (L << 12) | fl;
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sh.items[ci == 0 ? 2 : ci - 1] = 0u;
+      }
+      const uint32_t nitems = prune ? *cnt : nlane;
+      if (nitems == 0) return;  // nothing evaluated: no candidate (uniform)
+      {
+        const uint32_t tid = ftid();
+        for (uint32_t i = tid; i < nsl; i += nthr) slots[i] = 0ull;
+        __syncthreads();
+      }
+      {
+        // units (lane, width block, start group): lane-major pairs, every 64
+        // pairs taken once per start group by whole waves
+        const uint32_t tid = ftid();
+        constexpr uint32_t NH = K / sks<K>();
+        const uint32_t npairs = nitems * nbw;
+        const uint32_t nrun = (npairs + 63) / 64 * 64 * NH;
+        for (uint32_t r0 = 0; r0 < nrun; r0 += nthr) {
+          const uint32_t j = r0 + tid;
+          const uint32_t grp = j >> 6, half = grp % NH;
+          const uint32_t u = (grp / NH) * 64 + (j & 63);
+          const bool ok = j < nrun && u < npairs;
+          const uint32_t it = ok ? (prune ? items[u / nbw] : ((u / nbw) << 12)) : 0u;
+          const uint32_t bw = ok ? u % nbw : 0u;
+          if (ok && bw >= (it & 0xFFFu)) {
+            const uint32_t L = it >> 12;
+            const uint32_t q = R.wrap(gb + L);
+            unsigned long long *row = slots + (size_t)((L * K) / C) * zmax;
+            if constexpr (NH == 1) {
+              eval_unit<K, 0>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+            } else {
+              static_assert(NH == 4, "four start groups of four");
+              if (half == 0)
+                eval_unit<K, 0>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+              else if (half == 1)
+                eval_unit<K, 4>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+              else if (half == 2)
+                eval_unit<K, 8>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+              else
+                eval_unit<K, 12>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      const uint32_t tid = ftid(), ln = tid & 63, wv = tid >> 6;
+      if (search) {
+        // stage the tile's maxima in slot order, i.e. (chunk, width) order
+        const uint32_t per = (nsl + nthr - 1) / nthr;
+        const uint32_t lo = min(tid * per, nsl), hi = min(lo + per, nsl);
+        uint32_t mine = 0;
+        for (uint32_t i = lo; i < hi; ++i) mine += slots[i] != 0ull ? 1u : 0u;
+        uint32_t incl = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t v = __shfl_up(incl, o, 64);
+          if (ln >= (uint32_t)o) incl += v;
+        }
+        if (ln == 63) sh.wsum[wv] = incl;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (uint32_t v = 0; v < (uint32_t)kStreamWaves; ++v) {
+          before += v < wv ? sh.wsum[v] : 0u;
+          tot += sh.wsum[v];
+        }
+        if (tid == 0) sh.base = tot ? atomicAdd(pool_head, tot) : 0u;
+        __syncthreads();
+        const uint32_t base = sh.base;
+        uint32_t rank = before + incl - mine;
+        for (uint32_t i = lo; i < hi; ++i) {
+          const unsigned long long key = slots[i];
+          if (key == 0ull) continue;
+          const uint32_t pos = base + rank;
+          if (pos < pool_cap) {
+            const uint32_t cl = i / zmax, w = i - cl * zmax + 1;
+            StageEntry e;
+            e.unit = wg;
+            e.rank = wg_count + rank;
+            e.spec = (uint32_t)s;
+            e.bin = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+            e.power = sunord((uint32_t)(key >> 32));
+            e.width = w;
+            pool[pos] = e;
+          }
+          ++rank;
+        }
+        wg_count += tot;
+      } else {
+        for (uint32_t i = tid; i < nsl; i += nthr) {
+          const unsigned long long key = slots[i];
+          const size_t o = (size_t)chunk0 * zmax + i;
+          M_out[o] = key ? sunord((uint32_t)(key >> 32)) : -INFINITY;
+          I_out[o] = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : 0xFFFFFFFFu;
+        }
+      }
+      __syncthreads();
+    };
+
+    // Step j normalises batch j (wave w: block a + jNB + w) and banks every
+    // tile whose windows the ring then holds: up to f + NB - lgs, the
+    // batch's end less the halo (the next batch overwrites the blocks before
+    // f + NB - lag), and for the last batch up to b - lgs, so that the
+    // halo's slots are free.  The halo step then normalises the first bins of
+    // blocks b .. b+lgs-1 (wave w: block b + w) and banks up to b.  The next
+    // batch's loads (or the halo's) are in flight all along: the two register
+    // sets alternate.
+    auto step = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
+      const uint32_t f = a + j * NB;
+      const uint32_t k = f + wave;
+      if (k < b) {
+        NormOut o = no;
+        o.pub = (publish && k - a < zpub) ? pw + 4 * (k - a) : nullptr;
+        normalise<K, EPL, FP>(d, k, r, false, BlockStats{}, B, R, (k - a) % RB, o, lane);
+      }
+      __syncthreads();
+      const uint32_t ready = j + 1 == nbat ? (b > lgs ? b - lgs : 0u)
+                                           : (f + NB > lgs ? f + NB - lgs : 0u);
+      while (banked < ready) {
+        const uint32_t t1 = min(banked + NB, ready);
+        bank_tile(banked, t1);
+        banked = t1;
+      }
+    };
+    uint32_t j = 0;
+    while (true) {
+      step(j, cur);
+      if (j + 1 == nbat) break;  // the halo is in nxt
+      issue(j + 2, cur);
+      step(j + 1, nxt);
+      if (j + 2 == nbat) {  // the halo is in cur
+        nxt = cur;
+        break;
+      }
+      issue(j + 3, nxt);
+      j += 2;
+    }
+    {
+      // the halo step
+      const uint32_t k = b + wave;
+      if (wave < lgs) {
+        const uint32_t limit = min(B, (zc - wave * B + 63) / 64 * 64);
+        const uint32_t slot = (k - a) % RB;
+        if (k >= nbs) {
+          // no spectrum behind these bins
+          fill_past_end<K, EPL>(R, slot, limit, lane);
+        } else {
+          BlockStats given{};
+          bool use_given = false;
+          if constexpr (!FP) {
+            // the next range's published statistics, or our own
+            unsigned long long v = 0;
+            bool ok = false;
+            if (lane < 4) {
+              for (uint32_t it = 0; it < spin; ++it) {
+                v = __hip_atomic_load(hw + 4 * wave + lane, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)(v >> 32) == tag) {
+                  ok = true;
+                  break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+              }
+            }
+            use_given = __ballot(ok) == 0xFull;
+            if (use_given) {
+              given.med_re = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 0));
+              given.mad_re = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 1));
+              given.med_im = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 2));
+              given.mad_im = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 3));
+            } else {
+              load_block<EPL, FP>(d, k, nxt);
+            }
+          }
+          normalise<K, EPL, FP>(d, k, nxt, use_given, given, limit, R, slot, NormOut{}, lane);
+        }
+      }
+      __syncthreads();
+      while (banked < b) {
+        const uint32_t t1 = min(banked + NB, b);
+        bank_tile(banked, t1);
+        banked = t1;
+      }
+    }
+    gc = d.block_begin + b;
+    if (b == nbs) ++s;
+  }
+
+  // publish this range's count; the last workgroup scans every range's
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // the pool reservations are complete before the count is published, so
+    // the scan (which waits for every count) may re-arm the pool head
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_store(p.wg_word + wg, ((unsigned long long)tag << 32) | wg_count,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sh.lost = 0u;
+  }
+  if (wg != p.nwg - 1) return;
+  __syncthreads();
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (p.nwg + nthr - 1) / nthr;
+  const uint32_t lo = min(tid * per, p.nwg), hi = min(lo + per, p.nwg);
+  uint32_t mine = 0;
+  bool lost = false;
+  for (uint32_t i = lo; i < hi; ++i) {
+    unsigned long long v = 0;
+    bool ok = false;
+    for (uint32_t it = 0; it < p.spin; ++it) {
+      v = __hip_atomic_load(p.wg_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((uint32_t)(v >> 32) == tag) {
+        ok = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    lost |= !ok;
+    mine += ok ? (uint32_t)v : 0u;
+  }
+  if (lost) atomicOr(&sh.lost, 1u);
+  uint32_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += v;
+  }
+  if (lane == 63) sh.wsum[wave] = incl;
+  __syncthreads();
+  uint32_t run = 0, tot = 0;
+  for (uint32_t v = 0; v < (uint32_t)kStreamWaves; ++v) {
+    run += v < wave ? sh.wsum[v] : 0u;
+    tot += sh.wsum[v];
+  }
+  run += incl - mine;
+  for (uint32_t i = lo; i < hi; ++i) {
+    p.wg_prefix[i] = run;
+    run += (uint32_t)__hip_atomic_load(p.wg_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    p.wg_prefix[p.nwg] = tot;
+    if (search) {
+      *p.total = tot;
+      if (p.total2) *p.total2 = tot;
+      *p.overflow = sh.lost ? 2u : (tot > p.pool_cap ? 1u : 0u);
+    } else {
+      *p.overflow = sh.lost ? 2u : 0u;
+    }
+    __hip_atomic_store(p.pool_head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *gp(p.gen) = tag;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+
+constexpr size_t kStreamLdsMax = 64 * 1024 - 256;  // per workgroup, beside its static shared memory
+
+static uint32_t up16(uint32_t v) { return (v + 15u) & ~15u; }
+
+bool choose_stream_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, bool from_power,
+                            bool norm_exact, bool fp16, StreamGeometry *g) {
+  if (norm_exact || fp16) return false;
+  if (zmax_max == 0 || zmax_max > 4096 || C == 0 || C % 64 != 0) return false;
+  int K = 16;
+  while (K > 1 && (C / 64) % (uint32_t)K != 0) K /= 2;
+  if (K != 16 && K != 4) return false;
+  if (from_power) B = 1024;  // the streaming unit of power input
+  if (B != 256 && B != 1024) return false;
+  if (C > B || 64u * (uint32_t)K > B) return false;
+  const uint32_t zc = (zmax_max + K - 1) / K * K;
+  const uint32_t lag = (zc + B - 1) / B;
+  if (lag > (uint32_t)kStreamBatch) return false;
+  const uint32_t ring = kStreamBatch + lag;
+  const uint32_t gpb = B / K, ng = ring * gpb;
+  const uint32_t nblk = zc / K;
+  const uint32_t mirror = nblk + 2;
+  const uint32_t ne = K >= 16 ? 3 : K >= 8 ? 2 : 1;
+  const uint32_t pitch = 64 + 64 / K;
+  uint32_t off = 0;
+  const uint32_t ring_bytes = ring * (B / (64 * K)) * K * pitch * 4;
+  off = up16(ring_bytes);
+  g->off_sg = off;
+  off = up16(off + (ng + mirror) * 4);
+  g->off_ep = off;
+  off = up16(off + ne * (ng + mirror) * 4);
+  g->off_slots = off;
+  const uint32_t nch = kStreamBatch * B / C;
+  off = up16(off + nch * zmax_max * 8);
+  g->off_tl = off;
+  g->zc_pad = (zc + 3) / 4 * 4;
+  off = up16(off + (g->zc_pad + 4 + nblk + 4) * 4);
+  g->off_items = off;
+  off = up16(off + kStreamBatch * B / K * 4);
+  if (off > kStreamLdsMax) return false;
+  g->K = K;
+  g->EPL = (int)(B / 64);
+  g->lag = lag;
+  g->ring = ring;
+  g->mirror = mirror;
+  g->zc_max = zc;
+  g->lds_bytes = off;
+  return true;
+}
+
+template <int K, int EPL, bool FP>
+static const void *stream_fn() {
+  return reinterpret_cast<const void *>(&stream_kernel<K, EPL, FP>);
+}
+
+static const void *stream_entry(const StreamGeometry &g, bool fp) {
+  if (g.K == 16 && g.EPL == 16) return fp ? stream_fn<16, 16, true>() : stream_fn<16, 16, false>();
+  if (g.K == 4 && g.EPL == 16) return fp ? stream_fn<4, 16, true>() : stream_fn<4, 16, false>();
+  if (g.K == 4 && g.EPL == 4) return fp ? stream_fn<4, 4, true>() : stream_fn<4, 4, false>();
+  return nullptr;
+}
+
+int stream_occupancy(const StreamGeometry &g, bool from_power) {
+  const void *fn = stream_entry(g, from_power);
+  if (!fn) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kStreamThreads, g.lds_bytes) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+hipError_t launch_stream(const StreamParams &p, hipStream_t stream) {
+  const void *fn = stream_entry(p.g, p.from_power != 0);
+  if (!fn) return hipErrorInvalidValue;
+  void *args[] = {const_cast<StreamParams *>(&p)};
+  return hipLaunchKernel(fn, dim3(p.nwg), dim3(kStreamThreads), args, p.g.lds_bytes, stream);
+}
+
+}  // namespace pulscan

@@ -42,7 +42,7 @@ def nchunks(n, C):
                                     (5000, 1, 0)])
 def test_threshold_table_matches_oracle(ctx, oracle_lib, n, Z, ws):
     say(f"thresholds n={n} Z={Z} ws={ws}")
-    searched = [w for w in range(1, Z + 1) if ws == 0 or ((w - 1) > 0 and ((w - 1) & (w - 2)) == 0)]
+    searched = [w for w in range(1, Z + 1) if oracle_lib.width_is_searched(w, Z, ws)]
     nt = float(n * max(len(searched), 1))
     T = ctx.pulscan_threshold_table(Z, 6.0, nt, ws)
     for w in range(1, Z + 1):
