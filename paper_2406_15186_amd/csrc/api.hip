@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -21,32 +22,48 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// What a threshold table depends on.  Compared and hashed as bytes: every
+// member is 4 or 8 bytes wide and the struct has no padding.
 struct ThrKey {
-  bool valid = false;
-  uint32_t zmax = 0, zc = 0;
-  float sigma = 0.f;
-  double ntrials = 0.0;
-  int width_search = 0, debug = 0;
-  bool operator==(const ThrKey &o) const {
-    return valid && o.valid && zmax == o.zmax && zc == o.zc && sigma == o.sigma &&
-           ntrials == o.ntrials && width_search == o.width_search && debug == o.debug;
+  uint32_t zmax, zc, dofmul;
+  int32_t ws, debug;
+  float sigma;
+  double ntrials;
+  bool operator==(const ThrKey &o) const { return memcmp(this, &o, sizeof o) == 0; }
+};
+static_assert(sizeof(ThrKey) == 32, "no padding in the threshold key");
+struct ThrKeyHash {
+  size_t operator()(const ThrKey &k) const {
+    // FNV-1a over the key's bytes
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&k);
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < sizeof k; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return (size_t)h;
   }
 };
+
+// Device memory the threshold tables of a context occupy before the cache
+// is emptied and refilled (a soft limit: one launch may exceed it).
+constexpr size_t kThrCacheBytes = 64ull << 20;
+constexpr size_t kThrArenaBytes = 1ull << 20;
 
 }  // namespace
 
 struct pulscan_ctx {
   int device = 0;
-  DevBuf thr, pool, tile_word, tile_prefix, counters, outbuf, descs, jobs;
+  DevBuf pool, tile_word, tile_prefix, counters, outbuf, descs, jobs;
   DevBuf allbuf, hpow, hsum, hjobs;  // best-per-chunk scratch; harmonic power, sums, jobs
   DevBuf tune_out;                   // autotuner: candidate output of its timing runs
   DevBuf stats;                      // FP16 search: per-block statistics for the re-check
   DevBuf span_sum, span_prefix;      // two-level scan of many tiles
-  ThrKey thr_key;
+  // threshold tables: key -> device table, carved from arenas that live
+  // until the cache is emptied; thr_new lists the tables the last search
+  // launch added (forgotten again if that launch never ran)
+  std::unordered_map<ThrKey, float *, ThrKeyHash> thr_tab;
+  std::vector<ThrKey> thr_new;
+  std::vector<void *> thr_arenas;
+  size_t thr_used = 0, thr_cap = 0, thr_bytes = 0;
   // what the device holds for batched launches (re-uploaded only on change)
-  std::vector<ThreshJob> last_jobs;
-  float last_sigma = 0.f;
-  int last_ws = -1, last_debug = -1;
   std::vector<HarmJob> last_hjobs;
   // autotuner: (batch signature) -> (chunk, tile)
   std::vector<std::pair<std::vector<uint64_t>, std::pair<uint32_t, uint32_t>>> tuned;
@@ -163,6 +180,90 @@ int upload(pulscan_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream
   HIP_TRY(hipEventRecord(ctx->pinned_ev, stream));
   ctx->pinned_pending = true;
   return PULSCAN_OK;
+}
+
+void drop_graph(pulscan_ctx *ctx);
+
+// Empty the threshold cache (after the device has finished with its tables).
+int thr_clear(pulscan_ctx *ctx) {
+  HIP_TRY(hipDeviceSynchronize());
+  drop_graph(ctx);
+  for (void *p : ctx->thr_arenas) (void)hipFree(p);
+  ctx->thr_arenas.clear();
+  ctx->thr_tab.clear();
+  ctx->thr_new.clear();
+  ctx->thr_used = ctx->thr_cap = ctx->thr_bytes = 0;
+  ++ctx->epoch;
+  return PULSCAN_OK;
+}
+
+// Point every descriptor at its threshold table, reserving (and listing in
+// *jobs, for the threshold kernel) the tables the cache does not hold yet.
+// *zc_max gets the widest new table's width count.
+int thr_reserve(pulscan_ctx *ctx, std::vector<SpecDesc> &descs, float sigma, int ws, int debug,
+                std::vector<ThreshJob> *jobs, uint32_t *zc_max) {
+  ctx->thr_new.clear();
+  auto key_of = [&](const SpecDesc &d) {
+    ThrKey k;
+    memset(&k, 0, sizeof k);
+    k.zmax = d.zmax;
+    k.zc = d.zc;
+    k.dofmul = d.dofmul;
+    k.ws = ws;
+    k.debug = debug;
+    k.sigma = sigma;
+    k.ntrials = d.ntrials;
+    return k;
+  };
+  auto tab_bytes = [](uint32_t zc) { return ((size_t)zc * sizeof(float) + 255) & ~(size_t)255; };
+  // bytes of the tables missing (an upper bound: duplicates counted)
+  size_t need = 0;
+  for (const SpecDesc &d : descs)
+    if (!ctx->thr_tab.count(key_of(d))) need += tab_bytes(d.zc);
+  if (need && ctx->thr_bytes && ctx->thr_bytes + need > kThrCacheBytes) {
+    const int st = thr_clear(ctx);
+    if (st) return st;
+    need = 0;
+    for (const SpecDesc &d : descs) need += tab_bytes(d.zc);
+  }
+  *zc_max = 0;
+  for (SpecDesc &d : descs) {
+    const ThrKey k = key_of(d);
+    auto it = ctx->thr_tab.find(k);
+    if (it != ctx->thr_tab.end()) {
+      d.thr = it->second;
+      continue;
+    }
+    const size_t b = tab_bytes(d.zc);
+    if (ctx->thr_used + b > ctx->thr_cap) {
+      const size_t sz = need > kThrArenaBytes ? need : kThrArenaBytes;
+      void *p = nullptr;
+      if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return PULSCAN_ENOMEM;
+      }
+      ctx->thr_arenas.push_back(p);
+      ctx->thr_bytes += sz;
+      ctx->thr_used = 0;
+      ctx->thr_cap = sz;
+      ++ctx->epoch;
+    }
+    float *t = reinterpret_cast<float *>(static_cast<char *>(ctx->thr_arenas.back()) + ctx->thr_used);
+    ctx->thr_used += b;
+    need = need > b ? need - b : 0;
+    ctx->thr_tab.emplace(k, t);
+    ctx->thr_new.push_back(k);
+    d.thr = t;
+    jobs->push_back(ThreshJob{t, d.zmax, d.zc, d.ntrials, d.dofmul, 0u});
+    *zc_max = d.zc > *zc_max ? d.zc : *zc_max;
+  }
+  return PULSCAN_OK;
+}
+
+// Forget the tables the last search launch reserved: their kernel never ran.
+void thr_forget_new(pulscan_ctx *ctx) {
+  for (const ThrKey &k : ctx->thr_new) ctx->thr_tab.erase(k);
+  ctx->thr_new.clear();
 }
 
 bool is_pow4(uint64_t v) {
@@ -356,42 +457,34 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     zc_max = d.zc > zc_max ? d.zc : zc_max;
   }
 
-  // thresholds: table s at thr + s * zc_max, recomputed only when the batch's
-  // (zmax, ntrials, degrees of freedom) or sigma change
+  // thresholds: one cached device table per (zmax, ntrials, degrees of
+  // freedom, sigma, width search, debug); the tables this launch lacks are
+  // computed together, before the bank kernel, on the same stream
   int st = PULSCAN_OK;
   if (!power_only) {
-    const void *thr_before = ctx->thr.p;
-    st = grow(ctx, ctx->thr, (size_t)nspec * zc_max * sizeof(float), false);
-    if (st) return st;
-    if (ctx->thr.p != thr_before) ctx->last_jobs.clear();
-    float *thr = static_cast<float *>(ctx->thr.p);
-    for (int s = 0; s < nspec; ++s) descs[s].thr = thr + (size_t)s * zc_max;
-    std::vector<ThreshJob> jobs(nspec);
-    for (int s = 0; s < nspec; ++s)
-      jobs[s] = ThreshJob{const_cast<float *>(descs[s].thr), descs[s].zmax, descs[s].zc,
-                          descs[s].ntrials, descs[s].dofmul, 0u};
     const int debug = search ? 0 : 1;
-    // the FP16-stored search compares against thresholds kRecheckBand lower
+    // the FP16-stored search compares against thresholds kRecheckBand sigma lower
     const float tsig = fp16 ? a.sigma - kRecheckBand : a.sigma;
-    const bool same = ctx->last_jobs.size() == jobs.size() && ctx->last_sigma == tsig &&
-                      ctx->last_ws == ws && ctx->last_debug == debug &&
-                      memcmp(ctx->last_jobs.data(), jobs.data(), jobs.size() * sizeof(ThreshJob)) == 0;
-    if (!same) {
+    std::vector<ThreshJob> jobs;
+    uint32_t zc_new = 0;
+    st = thr_reserve(ctx, descs, tsig, ws, debug, &jobs, &zc_new);
+    if (st) return st;
+    if (!jobs.empty()) {
       const ThreshJob *jobs_dev = nullptr;
-      if (nspec > 1) {
+      if (jobs.size() > 1) {
         st = grow(ctx, ctx->jobs, jobs.size() * sizeof(ThreshJob), false);
         if (st) return st;
         st = upload(ctx, ctx->jobs.p, jobs.data(), jobs.size() * sizeof(ThreshJob), stream);
         if (st) return st;
         jobs_dev = static_cast<const ThreshJob *>(ctx->jobs.p);
       }
-      HIP_TRY(launch_thresholds(jobs_dev, jobs[0], nspec, zc_max, (double)tsig, ws, debug,
-                                stream));
+      if (launch_thresholds(jobs_dev, jobs[0], (int)jobs.size(), zc_new, (double)tsig, ws, debug,
+                            stream) != hipSuccess) {
+        (void)hipGetLastError();
+        thr_forget_new(ctx);
+        return PULSCAN_EHIP;
+      }
       ++ctx->epoch;
-      ctx->last_jobs = jobs;
-      ctx->last_sigma = tsig;
-      ctx->last_ws = ws;
-      ctx->last_debug = debug;
     }
   }
 
@@ -777,7 +870,7 @@ int run_graph(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs 
       (void)hipGetLastError();
       if (graph) (void)hipGraphDestroy(graph);
       // captured work never ran: forget what it would have put on the device
-      ctx->last_jobs.clear();
+      thr_forget_new(ctx);
       ctx->last_descs.clear();
       ctx->last_pdescs.clear();
       ctx->last_hjobs.clear();
@@ -847,6 +940,8 @@ int autotune(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
   sig.push_back((uint64_t)a.opts.width_search);
   sig.push_back((uint64_t)a.opts.dense);
   sig.push_back((uint64_t)a.opts.power_fp16);
+  sig.push_back((uint64_t)a.opts.norm);
+  sig.push_back(ctx->use_stream ? 1u : 0u);
   for (auto &e : ctx->tuned)
     if (e.first == sig) {
       *chunk_out = e.second.first;
@@ -876,7 +971,19 @@ int autotune(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
     st = grow(ctx, ctx->tune_out, (size_t)(worst + 1) * sizeof(pulscan_candidate), false);
     if (st) break;
     Counters *cnt = nullptr;
-    for (uint32_t T : tile_choices(C, B, zmax_max, a.opts.power_fp16 != 0)) {
+    // where the streaming kernel serves the search it is the only candidate
+    // (tile 0), so that a later call with the returned chunk and no tile
+    // runs the same kernel and reports the same bits
+    StreamGeometry sg{};
+    const bool from_power = a.opts.numharm > 1;
+    const bool sk = ctx->use_stream &&
+                    choose_stream_geometry(C, B, zmax_max, from_power,
+                                           a.opts.norm == PULSCAN_NORM_EXACT,
+                                           a.opts.power_fp16 != 0, &sg) &&
+                    stream_occ(ctx, sg, from_power) > 0;
+    const std::vector<uint32_t> tiles =
+        sk ? std::vector<uint32_t>{0u} : tile_choices(C, B, zmax_max, a.opts.power_fp16 != 0);
+    for (uint32_t T : tiles) {
       RunArgs t = a;
       t.chunk = C;
       t.block = B;
@@ -977,7 +1084,8 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
   (void)hipDeviceSynchronize();
   drop_graph(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-  DevBuf *bufs[] = {&ctx->thr,    &ctx->pool,   &ctx->tile_word, &ctx->tile_prefix,
+  for (void *p : ctx->thr_arenas) (void)hipFree(p);
+  DevBuf *bufs[] = {&ctx->pool,   &ctx->tile_word, &ctx->tile_prefix,
                     &ctx->counters, &ctx->outbuf, &ctx->descs,  &ctx->jobs,
                     &ctx->allbuf, &ctx->hpow,   &ctx->hsum,     &ctx->hjobs,
                     &ctx->tune_out, &ctx->stats,  &ctx->pdescs,

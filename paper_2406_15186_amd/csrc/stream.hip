@@ -1093,7 +1093,8 @@ bool choose_stream_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, bool from
   if (K != 16 && K != 4) return false;
   if (from_power) B = 1024;  // the streaming unit of power input
   if (B != 256 && B != 1024) return false;
-  if (C > B || 64u * (uint32_t)K > B) return false;
+  // a tile starts on a block boundary, so chunks must tile the block
+  if (C > B || B % C != 0 || 64u * (uint32_t)K > B) return false;
   const uint32_t zc = (zmax_max + K - 1) / K * K;
   const uint32_t lag = (zc + B - 1) / B;
   if (lag > (uint32_t)kStreamBatch) return false;
