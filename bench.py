@@ -37,9 +37,14 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # running sum and half of a three-input max (two comparisons per v_max3_f32)
 BANK_OPS_PER_BIN_WIDTH = 1.5
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_kernel_plain_2e23_traffic.json")
-BANK_SOURCE = os.path.join(ROOT, "paper_2406_15186_amd", "csrc", "stream.hip")
-BANK_KERNEL = "stream_kernel"
+# HBM bytes per launch of each bank kernel at the headline workload, from
+# committed rocprofv3 counter summaries (valid while the kernel's source is
+# the one the counters were taken on)
+KERNEL_NAMES = {0: "stream_kernel", 1: "bank_kernel"}   # PULSCAN_KERNEL_STREAM / _TILED
+TRAFFIC = {
+    "stream_kernel": ("stream_kernel_plain_2e23_traffic.json", "stream.hip"),
+    "bank_kernel": ("bank_kernel_plain_2e23_traffic.json", "bank.hip"),
+}
 
 TIMING_EVERY = 16           # bank launches per timed one (each timed launch costs ~5 us of step)
 SATURATED_REQUESTS = 20000  # the serving capacity run
@@ -50,15 +55,18 @@ C5_SAMPLES = 3              # spectra of the FP16 batch checked against the orac
 C5_SIGMA_BAND = 0.05
 
 
-def measured_traffic():
-    """HBM bytes per bank-kernel launch from the committed counter summary, or
-    None when there is none or the kernel source has changed since it was taken."""
+def measured_traffic(kname):
+    """HBM bytes per launch of bank kernel `kname` from its committed counter
+    summary, or None when there is none or the kernel's source has changed
+    since the counters were taken."""
     import hashlib
+    fname, source = TRAFFIC[kname]
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(os.path.join(ROOT, "profiles", fname)))
     except (OSError, ValueError):
         return None
-    src = hashlib.sha256(open(BANK_SOURCE, "rb").read()).hexdigest()
+    src = hashlib.sha256(open(os.path.join(ROOT, "paper_2406_15186_amd", "csrc", source),
+                              "rb").read()).hexdigest()
     if rec.get("bank_source_sha256") != src:
         return None
     return int(rec["bytes_per_launch"])
@@ -225,6 +233,7 @@ def batched_leg(ctx, pk, synth, args, stream, tone_power):
     per = [a.elapsed_time(b) for a, b in evs]
     ms = float(np.mean(per))
     assert int(cnt.item()) == n0, "graph replays disagree with the direct batched call"
+    bkernel = KERNEL_NAMES[ctx.pulscan_ctx_last_kernel()]
     ref = buf[: n0 * isz].cpu().numpy().view(pk.CANDIDATE_DTYPE).copy()
 
     # the same spectra one launch each; the first pass fills the threshold
@@ -315,7 +324,7 @@ def batched_leg(ctx, pk, synth, args, stream, tone_power):
             "unit": "G bin-widths/s", "ms_per_batch": round(ms, 4),
             "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
             "hbm_frac": round(8.0 * nb / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
-            "chunk": chunk, "graph": True, "candidates": n0,
+            "chunk": chunk, "graph": True, "candidates": n0, "kernel": bkernel,
             "plain_value": round(bw / (pms * 1e-3) / 1e9, 3), "plain_ms": round(pms, 4),
             "speedup_vs_plain": round(pms / ms, 3),
             "thresholds": "cached on both sides", "autotune_s": round(tune_s, 2),
@@ -475,6 +484,8 @@ def main():
     ap.add_argument("--cpu-single-bins", type=int, default=1 << 20)
     ap.add_argument("--dense", action="store_true",
                     help="evaluate every width block (no pruning bound): same candidates")
+    ap.add_argument("--kernel", choices=("auto", "stream", "tiled"), default="auto",
+                    help="bank kernel: the library's choice per launch (default), or one forced")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the log-z and four-harmonic searches of the headline spectrum")
     ap.add_argument("--no-batched", action="store_true",
@@ -507,6 +518,8 @@ def main():
     n, Z, C, sigma = wl.nbins, wl.zmax, wl.chunk, wl.sigma
     log(f"bench: workload {wl.name} nbins={n} zmax={Z} chunk={C} sigma={sigma}")
     ctx = pk.Context(0)
+    ctx.pulscan_ctx_set_kernel({"auto": pk.PULSCAN_KERNEL_AUTO, "stream": pk.PULSCAN_KERNEL_STREAM,
+                                "tiled": pk.PULSCAN_KERNEL_TILED}[args.kernel])
 
     def tone_power(A, w, nt):
         return float(ctx.pulscan_threshold_table(w, A, nt)[w - 1])
@@ -518,8 +531,9 @@ def main():
     ms_per_step, gpu_ms, bank_ms, ref_count = timed_steps(
         ctx, pk, d, Z, C, sigma, stream, args.steps, args.warmup, dense=args.dense)
     value = n * Z / (ms_per_step * 1e-3) / 1e9
+    kname = KERNEL_NAMES[ctx.pulscan_ctx_last_kernel()]
     log(f"bench: {ref_count} candidates per step; {ms_per_step:.4f} ms/step wall, "
-        f"{gpu_ms:.4f} ms/step GPU, bank kernel {bank_ms * 1e3:.1f} us")
+        f"{gpu_ms:.4f} ms/step GPU, bank kernel ({kname}) {bank_ms * 1e3:.1f} us")
 
     # synchronous single calls: per-call latency including the host round trip
     cap = ((n + C - 1) // C) * Z
@@ -540,7 +554,9 @@ def main():
                                      "four harmonics", numharm=4),
         }
 
-    small = latency_leg(ctx, pk, synth, tone_power, args.latency_calls)
+    small = None
+    if args.latency_calls > 0:
+        small = latency_leg(ctx, pk, synth, tone_power, args.latency_calls)
 
     if args.copy_reference_mib > 0:
         nb = args.copy_reference_mib << 20
@@ -578,14 +594,15 @@ def main():
         roofline = {"bound": "alu", "achieved": round(achieved, 3),
                     "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                    "kernel": BANK_KERNEL, "kernel_us": round(bank_ms * 1e3, 2),
+                    "kernel": kname, "kernel_us": round(bank_ms * 1e3, 2),
                     "ops_per_bin_width": BANK_OPS_PER_BIN_WIDTH}
     else:
         # pruned bank: one read of the complex spectrum, 8 bytes per bin
         achieved = 8.0 * n / (bank_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(), "kernel": BANK_KERNEL,
+                    "traffic": measured_traffic(kname),
+                    "kernel": kname,
                     "kernel_us": round(bank_ms * 1e3, 2), "bytes_per_bin": 8}
         if copy_gbs:
             roofline["copy_peak"] = round(copy_gbs, 1)
@@ -610,7 +627,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "nbins": n, "zmax": Z, "chunk": C, "sigma": sigma,
                    "tones": len(tones), "red_frac": wl.red_frac,
-                   "path": "plain, async, " + ("dense" if args.dense else "pruned")},
+                   "path": "plain, async, " + ("dense" if args.dense else "pruned"),
+                   "kernel": args.kernel},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hbm_frac_step": round(8.0 * n / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 5),

@@ -238,15 +238,21 @@ int pulscan_threshold_table(pulscan_ctx *ctx, int zmax, float sigma_thresh, doub
 int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable);
 int pulscan_ctx_kernel_time(pulscan_ctx *ctx, double *total_ms, uint64_t *launches);
 
-/* Which bank kernel the context launches.  kernel = PULSCAN_KERNEL_STREAM
- * (the default): the streaming kernel (persistent workgroups, each reading a
- * contiguous range of normalisation blocks once) for every search and
- * debug-table call it serves, the tiled kernel (one workgroup per tile, each
- * tile re-reading the block after it) for the rest; PULSCAN_KERNEL_TILED: the
- * tiled kernel always.  Both give the same candidates within the stated
- * tolerances (the FP32 summation orders differ).  EINVAL for other values. */
-enum { PULSCAN_KERNEL_STREAM = 0, PULSCAN_KERNEL_TILED = 1 };
+/* Which bank kernel the context launches.  Both kernels give the same
+ * candidates bit for bit (the same arithmetic, the same FP32 summation order);
+ * they differ in speed.  kernel = PULSCAN_KERNEL_AUTO (the default): the
+ * streaming kernel (persistent workgroups, each reading a contiguous range of
+ * normalisation blocks once) for launches of spectra with at least 64 blocks
+ * per resident workgroup (a DM-trial batch, a served batch), the tiled kernel
+ * (one workgroup per tile) for the rest; PULSCAN_KERNEL_STREAM: the streaming
+ * kernel wherever it serves the search (not: FP16 power, the exact median,
+ * shapes outside its geometry); PULSCAN_KERNEL_TILED: the tiled kernel
+ * always.  EINVAL for other values. */
+enum { PULSCAN_KERNEL_STREAM = 0, PULSCAN_KERNEL_TILED = 1, PULSCAN_KERNEL_AUTO = 2 };
 int pulscan_ctx_set_kernel(pulscan_ctx *ctx, int kernel);
+/* The bank kernel of the context's last launch (PULSCAN_KERNEL_STREAM or
+ * PULSCAN_KERNEL_TILED; -1 before the first) into *kernel.  EINVAL on null. */
+int pulscan_ctx_last_kernel(pulscan_ctx *ctx, int *kernel);
 
 /* Polls of a word another workgroup publishes (a count, or the statistics of
  * a halo block) before the streaming kernel gives up on it: a lost count

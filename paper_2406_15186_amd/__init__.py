@@ -31,6 +31,7 @@ PULSCAN_W_ALL = 0
 PULSCAN_W_LOG2 = 1
 PULSCAN_KERNEL_STREAM = 0
 PULSCAN_KERNEL_TILED = 1
+PULSCAN_KERNEL_AUTO = 2
 
 
 class pulscan_candidate(ctypes.Structure):
@@ -100,6 +101,7 @@ SIGNATURES = {
     "pulscan_ctx_set_timing": (_i, [_vp, _i]),
     "pulscan_ctx_kernel_time": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_uint64)]),
     "pulscan_ctx_set_kernel": (_i, [_vp, _i]),
+    "pulscan_ctx_last_kernel": (_i, [_vp, ctypes.POINTER(_i)]),
     "pulscan_ctx_set_spin": (_i, [_vp, ctypes.c_uint32]),
     "pulscan_server_config_default": (None, [ctypes.POINTER(pulscan_server_config)]),
     "pulscan_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(pulscan_server_config)]),
@@ -341,8 +343,14 @@ class Context:
         launch, N > 1 every N-th, False or 0 none."""
         _check(lib().pulscan_ctx_set_timing(self._ctx, int(enable)), "pulscan_ctx_set_timing")
 
+    def pulscan_ctx_last_kernel(self) -> int:
+        """The bank kernel of the last launch (PULSCAN_KERNEL_STREAM or _TILED; -1 before)."""
+        k = ctypes.c_int(-1)
+        _check(lib().pulscan_ctx_last_kernel(self._ctx, ctypes.byref(k)), "pulscan_ctx_last_kernel")
+        return int(k.value)
+
     def pulscan_ctx_set_kernel(self, kernel: int):
-        """PULSCAN_KERNEL_STREAM (default) or PULSCAN_KERNEL_TILED."""
+        """PULSCAN_KERNEL_AUTO (default), PULSCAN_KERNEL_STREAM or PULSCAN_KERNEL_TILED."""
         _check(lib().pulscan_ctx_set_kernel(self._ctx, int(kernel)), "pulscan_ctx_set_kernel")
 
     def pulscan_ctx_set_spin(self, polls: int):

@@ -12,9 +12,13 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libpulscan.so")
 SOURCES = ["api.hip", "bank.hip", "stream.hip", "signif.hip", "harmonic.hip", "serve.hip"]
-# Translation units built without NaN semantics (their inputs are finite):
-# the compiler may then fold cross-lane moves into DPP min/max instructions.
-NO_NANS = {"stream.hip"}
+# Per-translation-unit flags.  stream.hip: built without NaN semantics (its
+# inputs are finite), so that the compiler may fold cross-lane moves into DPP
+# min/max instructions; and without the atomic optimizer, which would turn
+# each LDS atomic whose address is the same in every lane into a loop over
+# the active lanes (one v_readlane and a scalar compare per lane) where the
+# LDS itself serialises the lanes in a few cycles.
+EXTRA = {"stream.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -23,8 +27,7 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
 
 def _compile(src: str) -> str:
     obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-    extra = ["-fno-honor-nans"] if src in NO_NANS else []
-    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

@@ -90,7 +90,8 @@ struct pulscan_ctx {
   // generation and the published halo statistics
   DevBuf wg_word, wg_prefix, gen, halo;
   int n_cu = 0;
-  bool use_stream = true;         // 0: always the tiled kernel (comparisons)
+  int kernel = PULSCAN_KERNEL_AUTO;  // which bank kernel serves a search (pulscan_ctx_set_kernel)
+  int last_kernel = -1;              // the bank kernel of the last launch
   uint32_t spin = kStreamSpin;    // polls of a cross-workgroup word before giving up
   std::vector<std::pair<uint64_t, int>> occ;  // (geometry key, workgroups per CU)
   // kernel timing: every timing-th bank launch (0: off)
@@ -368,6 +369,21 @@ struct Pending {
 // an earlier one never does), so it can run under stream capture.
 void drop_graph(pulscan_ctx *ctx);
 
+// Whether the streaming kernel serves a launch it can run.  Both kernels give
+// the same bits; in automatic mode the streaming kernel takes launches of
+// spectra long enough to keep every resident workgroup streaming (at least
+// kStreamAutoBlocks blocks each), where it reads each bin once, and the tiled
+// kernel the rest, whose tiles start all at once.
+constexpr uint64_t kStreamAutoBlocks = 64;
+bool wants_stream(const pulscan_ctx *ctx, const std::vector<SpecIn> &specs, uint32_t block,
+                  bool from_power, int occ) {
+  if (ctx->kernel == PULSCAN_KERNEL_STREAM) return true;
+  if (ctx->kernel == PULSCAN_KERNEL_TILED || from_power) return false;
+  uint64_t blocks = 0;
+  for (const SpecIn &s : specs) blocks += (s.n + block - 1) / block;
+  return blocks >= kStreamAutoBlocks * (uint64_t)occ * (uint64_t)ctx->n_cu;
+}
+
 // Workgroups of the streaming kernel resident per CU for this geometry
 // (cached per geometry).
 int stream_occ(pulscan_ctx *ctx, const StreamGeometry &g, bool from_power) {
@@ -400,10 +416,11 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   // power, and sizes outside the streaming kernel's geometry)
   StreamGeometry sgeo{};
   int occ = 0;
-  const bool sk = ctx->use_stream && !power_only && a.tile == 0 &&
-                      choose_stream_geometry(a.chunk, a.block, zmax_max, a.from_power, exact,
-                                             fp16, &sgeo) &&
-                      (occ = stream_occ(ctx, sgeo, a.from_power)) > 0;
+  const bool sk = !power_only && a.tile == 0 &&
+                  choose_stream_geometry(a.chunk, a.block, zmax_max, a.from_power, exact, fp16,
+                                         &sgeo) &&
+                  (occ = stream_occ(ctx, sgeo, a.from_power)) > 0 &&
+                  wants_stream(ctx, specs, 64u * (uint32_t)sgeo.EPL, a.from_power, occ);
   Geometry g{};
   if (sk) {
     g.K = sgeo.K;
@@ -631,8 +648,10 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     sp.P_out = a.P_out;
     sp.stats_out = a.stats_out;
     HIP_TRY(launch_stream(sp, stream));
+    ctx->last_kernel = PULSCAN_KERNEL_STREAM;
   } else {
     HIP_TRY(launch_bank(g, bp, tiles, stream));
+    ctx->last_kernel = PULSCAN_KERNEL_TILED;
   }
   if (e1) {
     HIP_TRY(hipEventRecord(e1, stream));
@@ -941,7 +960,7 @@ int autotune(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
   sig.push_back((uint64_t)a.opts.dense);
   sig.push_back((uint64_t)a.opts.power_fp16);
   sig.push_back((uint64_t)a.opts.norm);
-  sig.push_back(ctx->use_stream ? 1u : 0u);
+  sig.push_back((uint64_t)ctx->kernel);
   for (auto &e : ctx->tuned)
     if (e.first == sig) {
       *chunk_out = e.second.first;
@@ -976,11 +995,12 @@ int autotune(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &
     // runs the same kernel and reports the same bits
     StreamGeometry sg{};
     const bool from_power = a.opts.numharm > 1;
-    const bool sk = ctx->use_stream &&
-                    choose_stream_geometry(C, B, zmax_max, from_power,
+    int socc = 0;
+    const bool sk = choose_stream_geometry(C, B, zmax_max, from_power,
                                            a.opts.norm == PULSCAN_NORM_EXACT,
                                            a.opts.power_fp16 != 0, &sg) &&
-                    stream_occ(ctx, sg, from_power) > 0;
+                    (socc = stream_occ(ctx, sg, from_power)) > 0 &&
+                    wants_stream(ctx, specs, 64u * (uint32_t)sg.EPL, from_power, socc);
     const std::vector<uint32_t> tiles =
         sk ? std::vector<uint32_t>{0u} : tile_choices(C, B, zmax_max, a.opts.power_fp16 != 0);
     for (uint32_t T : tiles) {
@@ -1274,11 +1294,11 @@ int pulscan_ctx_set_timing(pulscan_ctx *ctx, int enable) {
 }
 
 int pulscan_ctx_set_kernel(pulscan_ctx *ctx, int kernel) {
-  if (!ctx || (kernel != PULSCAN_KERNEL_STREAM && kernel != PULSCAN_KERNEL_TILED))
+  if (!ctx || (kernel != PULSCAN_KERNEL_STREAM && kernel != PULSCAN_KERNEL_TILED &&
+               kernel != PULSCAN_KERNEL_AUTO))
     return PULSCAN_EINVAL;
-  const bool s = kernel == PULSCAN_KERNEL_STREAM;
-  if (s != ctx->use_stream) drop_graph(ctx);
-  ctx->use_stream = s;
+  if (kernel != ctx->kernel) drop_graph(ctx);
+  ctx->kernel = kernel;
   return PULSCAN_OK;
 }
 
@@ -1286,6 +1306,12 @@ int pulscan_ctx_set_spin(pulscan_ctx *ctx, uint32_t polls) {
   if (!ctx || polls < 1) return PULSCAN_EINVAL;
   if (polls != ctx->spin) drop_graph(ctx);
   ctx->spin = polls;
+  return PULSCAN_OK;
+}
+
+int pulscan_ctx_last_kernel(pulscan_ctx *ctx, int *kernel) {
+  if (!ctx || !kernel) return PULSCAN_EINVAL;
+  *kernel = ctx->last_kernel;
   return PULSCAN_OK;
 }
 

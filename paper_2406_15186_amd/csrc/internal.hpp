@@ -143,7 +143,7 @@ struct StreamGeometry {
   uint32_t mirror;    // group-sum entries repeated past the ring's end
   uint32_t zc_max;    // largest zmax rounded up to K
   uint32_t zc_pad;    // threshold floats reserved in LDS
-  uint32_t off_sg, off_ep, off_slots, off_tl, off_items;  // LDS byte offsets
+  uint32_t off_sg, off_ep, off_slots, off_tl, off_items, off_xs;  // LDS byte offsets
   size_t lds_bytes;
 };
 

@@ -5,9 +5,10 @@
 //
 //  * Streaming.  A workgroup's range (a run of blocks of one or more series)
 //    is taken a batch of kStreamBatch blocks at a time, one block per wave.
-//    The next batch's loads are in flight (in registers) while the current
-//    one is normalised and searched, so the HBM stream never waits for the
-//    search.  Normalised power goes to an LDS ring of blocks; a tile of
+//    The next batch's loads are issued as soon as the current batch has
+//    arrived and are in flight (in registers) while it is normalised and
+//    searched.  Every issue is the same number of unconditional loads, so
+//    that the compiler's wait counts never hold one batch for the next.  Normalised power goes to an LDS ring of blocks; a tile of
 //    blocks is searched once the ring holds every bin its windows reach
 //    (zmax - 1 bins past its end, `lag` blocks).
 //  * Halo.  The windows of a range's last tile reach into the next range,
@@ -24,9 +25,10 @@
 //    and DPP min/max operations.
 //  * Bank (section 2.2.5, appendix algorithm "Boxcar Filtering Process"): as
 //    in the tiled kernel, a per-lane upper bound on K starts' windows finds
-//    the first width block that might reach a threshold, and flagged lanes
-//    are evaluated exactly by the whole workgroup, in a canonical FP32 order
-//    (eval_unit) shared with the dense route.
+//    the first width block that might reach a threshold.  Flagged lanes are
+//    evaluated exactly, width-parallel, in units of 64 widths shared by the
+//    waves (exact_unit), in the canonical FP32 order that the dense route
+//    (eval_unit over every lane) also follows, so the two agree bit for bit.
 //  * Staging: each tile's (chunk, width) maxima that reach their thresholds
 //    are staged in order with their rank in the workgroup's range; the last
 //    workgroup scans the ranges' counts.
@@ -66,6 +68,9 @@ constexpr int kSBoundBatch = 8;
 // non-negative FP32 terms compared with T (1 - 2^-10) never skips a window
 // whose FP32 boxcar reaches T, for zmax <= 4096.
 constexpr float kSBoundSlack = 1.0f - 1.0f / 1024.0f;
+// s_waitcnt operand of "vmcnt(0)" on gfx9-family parts (vmcnt in bits 3:0
+// and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
 
 // ---------------------------------------------------------------------------
 // Median of medians
@@ -123,11 +128,11 @@ __device__ __forceinline__ void cross2(float x, float y, uint32_t lane, float &r
   rb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w), 32));
 }
 
-// The in-lane levels of one tree over the lane's EPL values (or their
-// magnitudes), doubled at each level.
-template <int EPL, bool ABS>
-__device__ __forceinline__ float lane_tree(const float (&v)[EPL]) {
-  auto f = [](float x) { return ABS ? fabsf(x) : x; };
+// The in-lane levels of one tree over the lane's EPL values (or, with DEV,
+// their distances |x - c| from c), doubled at each level.
+template <int EPL, bool DEV>
+__device__ __forceinline__ float lane_tree(const float (&v)[EPL], float c) {
+  auto f = [c](float x) { return DEV ? fabsf(x - c) : x; };
   if constexpr (EPL == 4) {
     return m4x2(f(v[0]), f(v[1]), f(v[2]), f(v[3]));
   } else {
@@ -143,40 +148,40 @@ struct BlockStats {
 };
 
 // Median-of-medians statistics of a block held as re[m], im[m] = element
-// lane + 64m; re and im become the deviations from their medians.
+// lane + 64m: the medians, then the medians of the distances from them.
 template <int EPL>
-__device__ __forceinline__ BlockStats block_stats(float (&re)[EPL], float (&im)[EPL], uint32_t lane) {
+__device__ __forceinline__ BlockStats block_stats(const float (&re)[EPL], const float (&im)[EPL],
+                                                  uint32_t lane) {
   // log4(EPL) in-lane levels and three cross-lane levels, each doubling
   constexpr float scale = EPL == 16 ? 1.0f / 32.0f : 1.0f / 16.0f;
   BlockStats s;
   float a, b;
-  cross2(lane_tree<EPL, false>(re), lane_tree<EPL, false>(im), lane, a, b);
+  cross2(lane_tree<EPL, false>(re, 0.f), lane_tree<EPL, false>(im, 0.f), lane, a, b);
   s.med_re = a * scale;
   s.med_im = b * scale;
-#pragma unroll
-  for (int m = 0; m < EPL; ++m) {
-    re[m] -= s.med_re;
-    im[m] -= s.med_im;
-  }
-  cross2(lane_tree<EPL, true>(re), lane_tree<EPL, true>(im), lane, a, b);
+  cross2(lane_tree<EPL, true>(re, s.med_re), lane_tree<EPL, true>(im, s.med_im), lane, a, b);
   s.mad_re = a * scale;
   s.mad_im = b * scale;
   return s;
 }
 
-// Normalised power of a deviation pair (section 2.2.3): each component
-// divided by its block's scaled MAD (0 when the MAD is 0), squared, summed.
+// Normalised power (section 2.2.3): each component less its block's median,
+// divided by its scaled MAD (0 when the MAD is 0), squared and summed.  The
+// tiled kernel evaluates it in the same operations, x / s - med / s as one
+// fused multiply-add, so the two kernels give the same power bit for bit.
 struct Scales {
-  float re, im;
+  float re, im, off_re, off_im;
 };
 __device__ __forceinline__ Scales scales_of(const BlockStats &s) {
   Scales c;
   c.re = s.mad_re > 0.f ? 1.0f / (s.mad_re * kMadScale) : 0.f;
   c.im = s.mad_im > 0.f ? 1.0f / (s.mad_im * kMadScale) : 0.f;
+  c.off_re = -s.med_re * c.re;
+  c.off_im = -s.med_im * c.im;
   return c;
 }
-__device__ __forceinline__ float power_of(float dre, float dim, const Scales &c) {
-  const float a = dre * c.re, b = dim * c.im;
+__device__ __forceinline__ float power_of(float re, float im, const Scales &c) {
+  const float a = fmaf(re, c.re, c.off_re), b = fmaf(im, c.im, c.off_im);
   return fmaf(a, a, b * b);
 }
 
@@ -341,31 +346,38 @@ __device__ __forceinline__ void load_block(const Series &d, uint32_t k, Raw<EPL,
   }
 }
 
-// The first `need` bins of block k (need a multiple of 64): a halo block
-// normalised with published statistics.  The series' partial last block is
-// loaded whole (its statistics window), as the normalisation expects.
+// The first `need` bins of block k (need a multiple of 64, at least 64): a
+// halo block normalised with published statistics.  Unconditional loads,
+// elements past `need` re-reading bin need - 1, so that every issue of a
+// batch is the same number of loads (the compiler can then wait for one set
+// while the next is in flight).  The series' partial last block is loaded
+// whole (its statistics window), as the normalisation expects.
 template <int EPL, bool FP>
 __device__ __forceinline__ void load_prefix(const Series &d, uint32_t k, uint32_t need,
                                             Raw<EPL, FP> &r) {
   constexpr uint32_t B = 64 * EPL;
-  const uint32_t own = fresh_u(k * B), nd = fresh_u(need);
-  if (own + B > d.n) {
-    load_block<EPL, FP>(d, k, r);
-    return;
+  const uint32_t own = fresh_u(k * B), n = d.n;
+  const bool partial = own + B > n;
+  if constexpr (FP) {
+    if (partial) {
+      load_block<EPL, FP>(d, k, r);
+      return;
+    }
   }
+  const uint32_t s0 = partial ? n - B : own;
+  const uint32_t lim = partial ? B : fresh_u(need);
   const uint32_t lane = ftid() & 63;
 #pragma unroll
   for (int m = 0; m < EPL; ++m) {
-    if (64u * m < nd) {  // uniform
-      if constexpr (FP) {
-        const float v = gp(reinterpret_cast<const float *>(d.x))[own + lane + 64 * m];
-        if (m & 1)
-          r.v[m / 2].y = v;
-        else
-          r.v[m / 2].x = v;
-      } else {
-        r.v[m] = gp(reinterpret_cast<const f32x2 *>(d.x))[own + lane + 64 * m];
-      }
+    const uint32_t i = s0 + min(lane + 64u * m, lim - 1u);
+    if constexpr (FP) {
+      const float v = gp(reinterpret_cast<const float *>(d.x))[i];
+      if (m & 1)
+        r.v[m / 2].y = v;
+      else
+        r.v[m / 2].x = v;
+    } else {
+      r.v[m] = gp(reinterpret_cast<const f32x2 *>(d.x))[i];
     }
   }
 }
@@ -408,11 +420,6 @@ __device__ __forceinline__ void normalise(const Series &d, uint32_t k, Raw<EPL, 
     BlockStats st;
     if (use_given) {
       st = given;
-#pragma unroll
-      for (int m = 0; m < EPL; ++m) {
-        re[m] -= st.med_re;
-        im[m] -= st.med_im;
-      }
     } else {
       st = block_stats<EPL>(re, im, lane);
       if (o.pub && lane < 4) {
@@ -522,38 +529,43 @@ __device__ __forceinline__ uint32_t sbound(const Ring<K> &R, uint32_t q, const f
 // bin0 = its first start), merging each width's maximum that reaches its
 // threshold into the chunk's slot (larger power wins, then the smaller bin).
 //
-// Canonical FP32 order of a boxcar.  With the lane's K starts s and the
-// window [s, s + w) ending at position p = s + w - 1 of the lane's groups:
+// Canonical FP32 order of a boxcar, the tiled kernel's: a start keeps a
+// running pair (hb, t) and each width adds the next bin to t, the window's
+// sum being hb + t; when the window reaches the end of a K-bin group, hb
+// takes that sum and t restarts from zero.  In closed form, with the window
+// [s, s + w) ending at position p = s + w - 1 of the lane's groups:
 //   * p < K (inside the lane's own group): the bins s..p summed from zero in
 //     increasing order;
 //   * otherwise, with the window ending in group g = p / K >= 1 at its
-//     e = p % K + 1-th bin:  Y = (H_s + G_g) + E_g(e),  where H_s sums the
-//     own group's bins K-1 down to s from zero, G_g sums the group sums of
-//     groups 1 .. g-1 from zero in increasing order (G_1 = 0, H_s + 0 = H_s),
-//     and E_g(e) sums group g's first e bins from zero in increasing order.
-// Both the dense and the pruned routes use this order (the dense route is
-// this function applied to every unit), so they agree bit for bit; any width
-// block can be entered from the group sums alone.  (Sums of non-negative
-// terms: every order is within (w - 1) u of the exact sum.)
+//     e = p % K + 1-th bin:  Y = HB(s, g) + E_g(e),  where HB(s, 1) = H_s
+//     sums the own group's bins s..K-1 from zero in increasing order,
+//     HB(s, g + 1) = HB(s, g) + Sg(g) adds group g's sum, and E_g(e) sums
+//     group g's first e bins from zero in increasing order (a group sum Sg is
+//     E_g(K)).
+// Both kernels and both routes (dense and pruned) follow this order, so they
+// agree bit for bit; any width block can be entered from the group sums
+// alone.  (Sums of non-negative terms: every order is within (w - 1) u of
+// the exact sum.)
 template <int K, int K0>
 __device__ __forceinline__ void eval_unit(const Ring<K> &R, uint32_t q, uint32_t b,
                                           const float *Tl, uint32_t zmax,
                                           unsigned long long *slot_row, uint32_t bin0) {
   constexpr int KS = sks<K>();
   constexpr int PITCH = spitch<K>();
-  // the lane's own bins K0 .. K-1 and H_s for s = K0 .. K0+KS-1
+  // H_s for s = K0 .. K0+KS-1, each from its own reads of the lane's bins
+  // (the barrier keeps one chain's loads in flight at a time)
   const float *po = R.bin(q, 0);
-  float own[K - K0];
-#pragma unroll
-  for (int j = K0; j < K; ++j) own[j - K0] = po[j * PITCH];
   float H[KS];
-  {
-    float h = 0.f;
 #pragma unroll
-    for (int j = K - 1; j >= K0; --j) {
-      h = j == K - 1 ? own[j - K0] : h + own[j - K0];
-      if (j < K0 + KS) H[j - K0] = h;
-    }
+  for (int k = 0; k < KS; ++k) {
+    asm volatile("" ::: "memory");
+    float v[K - K0];
+#pragma unroll
+    for (int j = K0 + k; j < K; ++j) v[j - K0] = po[j * PITCH];
+    float h = v[k];
+#pragma unroll
+    for (int j = K0 + k + 1; j < K; ++j) h = h + v[j - K0];
+    H[k] = h;
   }
   // prefix sums of the group after the window-end group's (EB: e = 1 .. K0+KS-1)
   constexpr int NB1 = K0 + KS - 1;
@@ -583,7 +595,10 @@ __device__ __forceinline__ void eval_unit(const Ring<K> &R, uint32_t q, uint32_t
     }
   };
   if (b == 0) {
-    // in-group windows by the recursion; crossing ones from H_s
+    // in-group windows by the recursion; crossing ones from HB(s, 1) = H_s
+    float own[K - K0];
+#pragma unroll
+    for (int j = K0; j < K; ++j) own[j - K0] = po[j * PITCH];
     float t[KS];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
@@ -601,14 +616,19 @@ __device__ __forceinline__ void eval_unit(const Ring<K> &R, uint32_t q, uint32_t
       merge(u, y);
     }
   } else {
-    float G = 0.f;
-    for (uint32_t j = 1; j < b; ++j) G = j == 1 ? R.Sg[q + 1] : G + R.Sg[q + j];
-    const float G1 = b == 1 ? R.Sg[q + 1] : G + R.Sg[q + b];
+    // HB(s, b) and HB(s, b + 1)
     float hA[KS], hB[KS];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      hA[k] = b == 1 ? H[k] : H[k] + G;
-      hB[k] = H[k] + G1;
+    for (int k = 0; k < KS; ++k) hA[k] = H[k];
+    for (uint32_t j = 1; j < b; ++j) {
+      const float sg = R.Sg[q + j];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) hA[k] = hA[k] + sg;
+    }
+    {
+      const float sg = R.Sg[q + b];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) hB[k] = hA[k] + sg;
     }
     float EA[K];
     {
@@ -632,6 +652,147 @@ __device__ __forceinline__ void eval_unit(const Ring<K> &R, uint32_t q, uint32_t
   }
 }
 
+// Exact evaluation of the widths of one pass, w0 .. w0 + 63 (w0 = fb K + 1 +
+// 64 pass), for the K starts of a flagged lane, by one wave, in the canonical
+// order above (so bit for bit what eval_unit and the tiled kernel give).
+// Thread t takes width w = w0 + t and runs over the lane's starts s: a window
+// ending at p = s + w - 1 >= K in group g = p / K, at its e = p % K + 1-th
+// bin, sums to HB(s, g) + E_g(e).  The unit first builds, in the wave's
+// scratch, HB(s, g) for the groups the pass reaches (lane s runs its chain
+// from H_s) and their prefix sums E_g (one lane per group), every chain with
+// its reads issued together; a window then costs two LDS reads, a select and
+// one addition.  Windows inside the lane's own group (p < K, first pass of
+// the first width block only) are summed by the recursion from their start,
+// one lane per start.  Each width's maximum over the starts (first start
+// attaining it) that reaches the threshold is merged into the chunk's slot.
+// A flagged lane's passes are independent units, so that the waves of the
+// workgroup share them.
+
+// Groups one pass of 64 widths reads, at most, and the scratch floats per
+// wave (their prefix sums, then HB of those groups and of the one after).
+template <int K>
+__host__ __device__ constexpr int xgroups() {
+  return (2 * K + 62) / K + 1;
+}
+template <int K>
+__host__ __device__ constexpr int xs_floats() {
+  return (xgroups<K>() * K + (xgroups<K>() + 1) * K + 15) / 16 * 16;
+}
+
+__device__ __forceinline__ unsigned long long slot_key(float y, uint32_t bin) {
+  return ((unsigned long long)sord(y) << 32) | (0xFFFFFFFFu - bin);
+}
+
+template <int K>
+__device__ __forceinline__ void exact_unit(const Ring<K> &R, uint32_t q, uint32_t fb,
+                                           uint32_t pass, const float *Tl, uint32_t zmax,
+                                           uint32_t nblk, unsigned long long *slot_row,
+                                           uint32_t bin0, float *xs, uint32_t lane) {
+  constexpr int PITCH = spitch<K>();
+  constexpr int NG = xgroups<K>();
+  float *const Q = xs;            // prefix sums of the unit's groups, flat by p
+  float *const HBt = xs + NG * K;  // HB(s, g) at (g - glo) K + s
+  const float *po = R.bin(q, 0);
+  const uint32_t w0 = fb * K + 1 + 64 * pass;
+  // groups glo..ghi hold every window end p >= K of the unit
+  const uint32_t glo = (w0 - 1) / K > 1u ? (w0 - 1) / K : 1u;
+  const uint32_t last = min(w0 + 63u, zmax);
+  const uint32_t ghi = min((last + K - 2) / K, nblk);
+  lds_wait();  // the previous unit's reads of the scratch are done
+  // (the barriers below keep eight loads in flight at a time: the batch of
+  // spectrum loads in flight holds many registers)
+  if (lane < (uint32_t)K) {
+    // H_s: lane s sums its group's bins s..K-1 from zero in increasing order
+    float h = 0.f;
+#pragma unroll
+    for (int j0 = 0; j0 < K; j0 += 8) {
+      asm volatile("" ::: "memory");
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8 && j0 + k < K; ++k) v[k] = po[(j0 + k) * PITCH];
+#pragma unroll
+      for (int k = 0; k < 8 && j0 + k < K; ++k) {
+        const uint32_t j = j0 + k;
+        if (j >= lane) h = j == lane ? v[k] : h + v[k];
+      }
+    }
+    // HB(s, g) for g = 1 .. ghi + 1, kept for g >= glo
+    float hb = h;
+    for (uint32_t g0 = 1; g0 <= ghi + 1; g0 += 8) {
+      asm volatile("" ::: "memory");
+      float sg[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sg[k] = R.Sg[q + min(g0 + k, ghi)];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t g = g0 + k;
+        if (g <= ghi + 1) {
+          if (g >= glo) HBt[(g - glo) * K + lane] = hb;
+          if (g <= ghi) hb = hb + sg[k];
+        }
+      }
+    }
+  }
+  if (lane <= ghi - glo) {
+    // prefix sums of group glo + lane, from zero in order
+    const float *pg = R.bin(R.wrap(q + glo + lane), 0);
+    float e = 0.f;
+#pragma unroll
+    for (int j0 = 0; j0 < K; j0 += 8) {
+      asm volatile("" ::: "memory");
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8 && j0 + k < K; ++k) v[k] = pg[(j0 + k) * PITCH];
+#pragma unroll
+      for (int k = 0; k < 8 && j0 + k < K; ++k) {
+        e = j0 + k == 0 ? v[0] : e + v[k];
+        Q[lane * K + j0 + k] = e;
+      }
+    }
+  }
+  if (pass == 0 && fb == 0 && lane < (uint32_t)K) {
+    // windows inside the own group: lane s sums from its start, in order
+    float t = 0.f;
+#pragma unroll
+    for (int u0 = 0; u0 < K; u0 += 8) {
+      asm volatile("" ::: "memory");
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8 && u0 + k < K; ++k)
+        v[k] = po[min(lane + u0 + k, (uint32_t)K - 1) * PITCH];
+#pragma unroll
+      for (int k = 0; k < 8 && u0 + k < K; ++k) {
+        const int u = u0 + k;
+        t = u == 0 ? v[0] : t + v[k];
+        if (lane + u < (uint32_t)K && (uint32_t)u < zmax && t >= Tl[u])
+          atomicMax(&slot_row[u], slot_key(t, bin0 + lane));
+      }
+    }
+  }
+  lds_wait();
+  const uint32_t w = w0 + lane;
+  if (w <= last) {
+    const uint32_t wm = w - 1, r = wm % K;
+    const float *h0 = HBt + (wm / K - glo) * K;  // HB of the window's end group when s + r < K
+    const float *qp = Q + (wm - glo * K);
+    float m = -INFINITY;
+    uint32_t best = 0;
+    const bool head = w0 <= (uint32_t)K;  // uniform: windows inside the own group exist
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      if (s % 8 == 0 && s > 0) asm volatile("" ::: "memory");
+      const float hb = s + r >= (uint32_t)K ? h0[K + s] : h0[s];
+      const float y = hb + qp[s];
+      const bool ok = !head || wm + s >= (uint32_t)K;
+      if (ok && y > m) {
+        m = y;
+        best = (uint32_t)s;
+      }
+    }
+    if (m >= Tl[wm]) atomicMax(&slot_row[wm], slot_key(m, bin0 + best));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The kernel
 
@@ -642,10 +803,15 @@ struct Shared {
   uint32_t wsum[kStreamWaves];
 };
 
+// Descriptors are read through the scalar cache (constant address space):
+// wave-uniform values in scalar registers, whose loads are counted apart from
+// the spectrum's vector loads, so that addresses built from them never wait
+// for the spectrum.
+#define CAS __attribute__((address_space(4)))
 __device__ __forceinline__ Series series_at(const SpecDesc *descs, int s) {
   static_assert(sizeof(SpecDesc) % 8 == 0, "descriptor of whole words");
   constexpr int W = sizeof(SpecDesc) / 8;
-  const GAS unsigned long long *g = gp(reinterpret_cast<const unsigned long long *>(descs + s));
+  const CAS unsigned long long *g = (const CAS unsigned long long *)(descs + s);
   unsigned long long w[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) w[k] = g[k];
@@ -715,7 +881,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     int lo = 0, hi = nspec - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (gp(descs)[mid].block_begin <= g0)
+      if (((const CAS SpecDesc *)descs)[mid].block_begin <= g0)
         lo = mid;
       else
         hi = mid - 1;
@@ -742,9 +908,34 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     const bool consume = b < nbs;                // our last tile reaches into the next range
     const uint32_t zpub = min(lgs, b - a);
 
+    // this series' first thresholds, then the first two batches' loads
+    // (loads complete in order, so the thresholds can be stored before the
+    // spectrum arrives), then the set-up
+    const float thr0 = threadIdx.x < zc ? gp(d.thr)[threadIdx.x] : 0.f;
+    const uint32_t nbat = (b - a + NB - 1) / NB;
+    Raw<EPL, FP> cur, nxt;
+    // issue the loads of batch j into r: block a + jNB + wave, or, for
+    // j == nbat, the halo block b + wave's first bins
+    // Every wave issues the same number of loads on every path (a wave with
+    // no block re-reads the range's last one, never used), so that waiting
+    // for one set never waits for the next.
+    auto issue = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
+      if (j < nbat) {
+        load_block<EPL, FP>(d, min(a + j * NB + wave, b - 1), r);
+      } else {
+        const bool halo = j == nbat && consume && wave < lgs && b + wave < nbs;
+        const uint32_t need = halo ? min(B, (zc - wave * B + 63) / 64 * 64) : B;
+        load_prefix<EPL, FP>(d, halo ? b + wave : b - 1, need, r);
+      }
+    };
+    issue(0, cur);
+
     // thresholds of the series, and the bound's minima of them
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < zc; i += nthr) Tl[i] = gp(d.thr)[i];
+    if (threadIdx.x < zc) Tl[threadIdx.x] = thr0;
+    if (zc > nthr) {  // zmax above 512 (uniform)
+      for (uint32_t i = ftid() + nthr; i < zc; i += nthr) Tl[i] = gp(d.thr)[i];
+    }
     __syncthreads();
     {
       // the first block's sub-ranges, widths 1..4, 5..8, 9..16 (those that
@@ -773,25 +964,6 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     // the halo's statistics words, published by the next range's workgroup
     const unsigned long long *hw = halo + (size_t)(wg + 1) * lag * 4;
     unsigned long long *pw = halo + (size_t)wg * lag * 4;
-
-    const uint32_t nbat = (b - a + NB - 1) / NB;
-    Raw<EPL, FP> cur, nxt;
-    // issue the loads of batch j into r: block a + jNB + wave, or, for
-    // j == nbat, the halo block b + wave's first bins
-    auto issue = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
-      // r's previous contents are dead on every path (so that the compiler
-      // does not keep them alive beside the set in flight)
-      r = Raw<EPL, FP>{};
-      if (j < nbat) {
-        const uint32_t k = a + j * NB + wave;
-        if (k < b) load_block<EPL, FP>(d, k, r);
-      } else if (j == nbat && consume && wave < lgs && b + wave < nbs) {
-        const uint32_t need = min(B, (zc - wave * B + 63) / 64 * 64);
-        load_prefix<EPL, FP>(d, b + wave, need, r);
-      }
-    };
-    issue(0, cur);
-    issue(1, nxt);
 
     uint32_t banked = a;
     no.tag = tag;
@@ -835,7 +1007,21 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         for (uint32_t i = tid; i < nsl; i += nthr) slots[i] = 0ull;
         __syncthreads();
       }
-      {
+      if (prune) {
+        // units (flagged lane, pass of 64 widths from its first flagged
+        // width block), one per wave at a time; a lane's passes go to
+        // consecutive waves
+        float *xs = reinterpret_cast<float *>(lds + p.g.off_xs) + wave * xs_floats<K>();
+        const uint32_t ln = ftid() & 63;
+        const uint32_t np = (zmax + 63) / 64;
+        for (uint32_t u = wave; u < nitems * np; u += kStreamWaves) {
+          const uint32_t it = items[u / np], pass = u % np, fb = it & 0xFFFu;
+          if (fb * K + 1 + 64 * pass > zmax) continue;  // past the lane's widths (uniform)
+          const uint32_t L = it >> 12;
+          exact_unit<K>(R, R.wrap(gb + L), fb, pass, Tl, zmax, nblk,
+                        slots + (size_t)((L * K) / C) * zmax, tb0 + L * K, xs, ln);
+        }
+      } else {
         // units (lane, width block, start group): lane-major pairs, every 64
         // pairs taken once per start group by whole waves
         const uint32_t tid = ftid();
@@ -929,8 +1115,10 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     // f + NB - lag), and for the last batch up to b - lgs, so that the
     // halo's slots are free.  The halo step then normalises the first bins of
     // blocks b .. b+lgs-1 (wave w: block b + w) and banks up to b.  The next
-    // batch's loads (or the halo's) are in flight all along: the two register
-    // sets alternate.
+    // batch's loads (or the halo's) are issued once this batch's data are in,
+    // and are in flight while it is searched: the two register sets
+    // alternate.  (Issued together, two batches would arrive interleaved,
+    // the whole range at once, with nothing to search in the meantime.)
     auto step = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
       const uint32_t f = a + j * NB;
       const uint32_t k = f + wave;
@@ -948,17 +1136,23 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         banked = t1;
       }
     };
+    // every load issued so far (the batch in r) has arrived
+    auto arrived = []() __attribute__((always_inline)) {
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    };
     uint32_t j = 0;
     while (true) {
+      arrived();
+      issue(j + 1, nxt);
       step(j, cur);
       if (j + 1 == nbat) break;  // the halo is in nxt
+      arrived();
       issue(j + 2, cur);
       step(j + 1, nxt);
       if (j + 2 == nbat) {  // the halo is in cur
         nxt = cur;
         break;
       }
-      issue(j + 3, nxt);
       j += 2;
     }
     {
@@ -1010,6 +1204,9 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     }
     gc = d.block_begin + b;
     if (b == nbs) ++s;
+    // every load of this series has been consumed: say so, so that the next
+    // series' loads are not held back for ones that might be in flight
+    __builtin_amdgcn_s_waitcnt(0);
   }
 
   // publish this range's count; the last workgroup scans every range's
@@ -1080,7 +1277,9 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
 // ---------------------------------------------------------------------------
 // Host side
 
-constexpr size_t kStreamLdsMax = 64 * 1024 - 256;  // per workgroup, beside its static shared memory
+// LDS per workgroup, beside its static shared memory: two workgroups share a
+// CU's 160 KiB
+constexpr size_t kStreamLdsMax = 80 * 1024 - 512;
 
 static uint32_t up16(uint32_t v) { return (v + 15u) & ~15u; }
 
@@ -1119,6 +1318,8 @@ bool choose_stream_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, bool from
   off = up16(off + (g->zc_pad + 4 + nblk + 4) * 4);
   g->off_items = off;
   off = up16(off + kStreamBatch * B / K * 4);
+  g->off_xs = off;
+  off = up16(off + kStreamWaves * (K == 16 ? xs_floats<16>() : xs_floats<4>()) * 4);
   if (off > kStreamLdsMax) return false;
   g->K = K;
   g->EPL = (int)(B / 64);
@@ -1142,9 +1343,20 @@ static const void *stream_entry(const StreamGeometry &g, bool fp) {
   return nullptr;
 }
 
+// Workgroups above 64 KiB of LDS must say so before they launch.
+static bool allow_lds(const void *fn, size_t bytes) {
+  if (bytes <= 64 * 1024) return true;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
 int stream_occupancy(const StreamGeometry &g, bool from_power) {
   const void *fn = stream_entry(g, from_power);
-  if (!fn) return 0;
+  if (!fn || !allow_lds(fn, g.lds_bytes)) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kStreamThreads, g.lds_bytes) !=
       hipSuccess) {
@@ -1156,7 +1368,7 @@ int stream_occupancy(const StreamGeometry &g, bool from_power) {
 
 hipError_t launch_stream(const StreamParams &p, hipStream_t stream) {
   const void *fn = stream_entry(p.g, p.from_power != 0);
-  if (!fn) return hipErrorInvalidValue;
+  if (!fn || !allow_lds(fn, p.g.lds_bytes)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StreamParams *>(&p)};
   return hipLaunchKernel(fn, dim3(p.nwg), dim3(kStreamThreads), args, p.g.lds_bytes, stream);
 }

@@ -17,9 +17,8 @@ CSRC = os.path.join(ROOT, "paper_2406_15186_amd", "csrc")
 @pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not installed")
 @pytest.mark.parametrize("src", ["bank.hip", "stream.hip", "signif.hip", "harmonic.hip"])
 def test_kernels_do_not_spill(tmp_path, src):
-    from paper_2406_15186_amd.build import FLAGS, NO_NANS
-    extra = ["-fno-honor-nans"] if src in NO_NANS else []
-    cmd = ["hipcc", *FLAGS, *extra, "-Rpass-analysis=kernel-resource-usage", "-c",
+    from paper_2406_15186_amd.build import EXTRA, FLAGS
+    cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-Rpass-analysis=kernel-resource-usage", "-c",
            os.path.join(CSRC, src), "-o", str(tmp_path / "k.o")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]

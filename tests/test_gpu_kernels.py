@@ -1,0 +1,107 @@
+"""The two bank kernels give the same bits.
+
+The tiled kernel (one workgroup per tile) and the streaming kernel
+(persistent workgroups over contiguous block ranges) normalise with the same
+operations and sum every boxcar in the same canonical FP32 order, so the
+library may pick either per launch.  Candidate lists, dense per-chunk tables
+and normalised powers are compared byte for byte, forcing each kernel in turn
+on the same spectra: the small and the paper-scale shapes, ragged lengths,
+logarithmic width sampling, the dense route and a batch.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import say, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2406_15186_amd as pk
+    pk.lib()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    import torch
+    assert torch.cuda.is_available()
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def spectrum(oracle_lib, n, Z, C, seed, tones=3, red=0.0):
+    wl = synth.Workload(f"kern_{seed}", n, Z, C, 6.0, seed, tones, None, (1, min(Z - 1, 60)),
+                        (8.0, 15.0), (1000, max(1001, n - Z - 2)), red_frac=red)
+    x, _ = synth.make_spectrum(wl, oracle_lib.power_for_sigma, nbins=n)
+    return x
+
+
+def both(ctx, pk, fn):
+    out = []
+    for k in (pk.PULSCAN_KERNEL_TILED, pk.PULSCAN_KERNEL_STREAM):
+        ctx.pulscan_ctx_set_kernel(k)
+        out.append(fn())
+    ctx.pulscan_ctx_set_kernel(pk.PULSCAN_KERNEL_AUTO)
+    return out
+
+
+CASES = [
+    # n, zmax, chunk, options
+    (1 << 16, 64, 256, {}),
+    (1 << 16, 64, 256, {"dense": True}),
+    ((1 << 18) + 37, 200, 1024, {}),
+    ((1 << 18) + 37, 200, 1024, {"dense": True}),
+    (1 << 20, 200, 1024, {"width_search": 1}),
+    ((1 << 19) + 4099, 300, 1024, {}),
+    (300000, 32, 256, {"norm_block": 1024}),
+]
+
+
+@pytest.mark.parametrize("n,Z,C,kw", CASES)
+def test_kernels_give_identical_candidates(ctx, pk, oracle_lib, n, Z, C, kw):
+    x = spectrum(oracle_lib, n, Z, C, seed=n % 97 + Z, red=0.01)
+    d = to_device(x)
+    say(f"kernels n={n} Z={Z} C={C} {kw}")
+    opts = pk.make_opts(**kw)
+    (a, na), (b, nb) = both(ctx, pk, lambda: ctx.pulscan_search_ex(d, Z, C, 6.0, opts=opts))
+    assert na == nb and na > 0
+    assert a.tobytes() == b.tobytes(), "tiled and streaming kernels differ"
+
+
+@pytest.mark.parametrize("n,Z,C", [(1 << 16, 64, 256), ((1 << 18) + 37, 200, 1024)])
+def test_kernels_give_identical_tables(ctx, pk, oracle_lib, n, Z, C):
+    x = spectrum(oracle_lib, n, Z, C, seed=5 + Z)
+    d = to_device(x)
+    (ta, tb) = both(ctx, pk, lambda: [t.cpu().numpy() for t in ctx.pulscan_debug_tables(d, Z, C)
+                                      if t is not None])
+    assert len(ta) == len(tb) >= 2
+    for i, (u, v) in enumerate(zip(ta, tb)):
+        assert u.tobytes() == v.tobytes(), i
+
+
+def test_kernels_give_identical_batches(ctx, pk, oracle_lib):
+    xs = [spectrum(oracle_lib, n, z, 1024, seed=40 + s)
+          for s, (n, z) in enumerate([(1 << 17, 64), (200001, 200), (1 << 18, 128)])]
+    ds = [to_device(x) for x in xs]
+    zs = [64, 200, 128]
+    (a, na, ca), (b, nb, cb) = both(ctx, pk, lambda: ctx.pulscan_search_batched(ds, zs, 1024, 6.0))
+    assert na == nb and ca == cb == 1024
+    assert a.tobytes() == b.tobytes()
+    # and every spectrum of the batch as its own search
+    parts = []
+    for s, (d, z) in enumerate(zip(ds, zs)):
+        g, _ = ctx.pulscan_search_ex(d, z, 1024, 6.0)
+        g["spectrum"] = s
+        parts.append(g)
+    assert np.concatenate(parts).tobytes() == a.tobytes()
+
+
+def test_set_kernel_rejects_unknown_values(ctx, pk):
+    with pytest.raises(pk.PulscanError) as e:
+        ctx.pulscan_ctx_set_kernel(7)
+    assert e.value.status == pk.PULSCAN_EINVAL
