@@ -261,6 +261,32 @@ int pulscan_ctx_last_kernel(pulscan_ctx *ctx, int *kernel);
  * value forces the give-up paths in tests.  polls >= 1, else EINVAL. */
 int pulscan_ctx_set_spin(pulscan_ctx *ctx, uint32_t polls);
 
+/* The single-spectrum search of pulscan_search_ex for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or other
+ * allocating routine and needs no context: every buffer its kernels use
+ * (threshold table, candidate staging, counters, per-workgroup words) lives
+ * in one static device array of about 25 MiB, which each GPU the library
+ * runs on holds until the process ends.
+ *   spectrum, nbins, zmax, chunk, sigma_thresh, opts: as pulscan_search_ex,
+ *     on the device current at the call, on opts->stream.
+ *   out: on_device must be 1 (the candidates go straight to out->data); with
+ *     opts->async, out->count_device receives the count and the call returns
+ *     once the work is queued; otherwise the call waits and sets out->count.
+ * Limits (PULSCAN_EUNSUPPORTED beyond them, before any launch): the shapes
+ * of the streaming bank kernel -- median-of-medians normalisation, chunk 256
+ * with 256- or 1024-bin blocks or chunk 1024 with 1024-bin blocks, zmax at
+ * most what one LDS ring holds (<= 4096) -- and numharm 1, no FP16 power, no
+ * best_per_chunk, no library graph mode.  At most 2^20 candidates are staged per call: more
+ * return PULSCAN_ENOMEM (out->count still gets the true total).  Other
+ * errors as pulscan_search_ex; EINVAL for a host output buffer.
+ * The thresholds are recomputed on every call (no table cache).  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (on two
+ * streams or two host threads) race and give undefined results. */
+int pulscan_search_noalloc(const pulscan_complex *spectrum, size_t nbins, int zmax, int chunk,
+                           float sigma_thresh, const pulscan_opts *opts,
+                           pulscan_candidates *out);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: spectra searched as they arrive.                                */
 /* ---------------------------------------------------------------------- */

@@ -103,6 +103,8 @@ SIGNATURES = {
     "pulscan_ctx_set_kernel": (_i, [_vp, _i]),
     "pulscan_ctx_last_kernel": (_i, [_vp, ctypes.POINTER(_i)]),
     "pulscan_ctx_set_spin": (_i, [_vp, ctypes.c_uint32]),
+    "pulscan_search_noalloc": (_i, [_vp, ctypes.c_size_t, _i, _i, _f, ctypes.POINTER(pulscan_opts),
+                                    ctypes.POINTER(pulscan_candidates)]),
     "pulscan_server_config_default": (None, [ctypes.POINTER(pulscan_server_config)]),
     "pulscan_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(pulscan_server_config)]),
     "pulscan_server_destroy": (None, [_vp]),
@@ -194,6 +196,29 @@ def make_opts(norm: int = PULSCAN_NORM_MOM, norm_block: int = 0, ntrials: float 
     if stream is not None:
         o.stream = stream if isinstance(stream, int) else stream.cuda_stream
     return o
+
+
+def pulscan_search_noalloc(spectrum, zmax: int, chunk: int, sigma_thresh: float, out_device,
+                           capacity: Optional[int] = None, opts: Optional[pulscan_opts] = None,
+                           count_device=None) -> int:
+    """The no-allocation search of one device spectrum into ``out_device`` (a
+    CUDA uint8 tensor of capacity*32 bytes).  Returns the true count (0 for
+    an asynchronous call, whose count goes to ``count_device``)."""
+    ptr, n = _spectrum_ptr(spectrum)
+    if opts is None:
+        opts = pulscan_opts_default()
+    if capacity is None:
+        capacity = out_device.numel() // CANDIDATE_DTYPE.itemsize
+    out = pulscan_candidates()
+    out.data = out_device.data_ptr()
+    out.on_device = 1
+    out.capacity = capacity
+    if count_device is not None:
+        out.count_device = count_device.data_ptr()
+    st = lib().pulscan_search_noalloc(ptr, n, zmax, chunk, sigma_thresh, ctypes.byref(opts),
+                                      ctypes.byref(out))
+    _check(st, "pulscan_search_noalloc", allow_overflow=True)
+    return int(out.count)
 
 
 class Context:

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libpulscan.so")
-SOURCES = ["api.hip", "bank.hip", "stream.hip", "signif.hip", "harmonic.hip", "serve.hip"]
+SOURCES = ["api.hip", "bank.hip", "stream.hip", "signif.hip", "harmonic.hip", "serve.hip",
+           "noalloc.hip"]
 # Per-translation-unit flags.  stream.hip: built without NaN semantics (its
 # inputs are finite), so that the compiler may fold cross-lane moves into DPP
 # min/max instructions; and without the atomic optimizer, which would turn

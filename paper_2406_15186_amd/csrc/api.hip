@@ -1054,6 +1054,13 @@ pulscan_ctx *g_default = nullptr;
 
 }  // namespace
 
+namespace pulscan {
+int check_search_args(const void *x, uint64_t n, int zmax, int chunk, const pulscan_opts &o,
+                      uint32_t *block) {
+  return check_spectrum(x, n, zmax, chunk, o, block);
+}
+}  // namespace pulscan
+
 extern "C" {
 
 const char *pulscan_strerror(int status) {

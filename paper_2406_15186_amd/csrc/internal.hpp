@@ -282,6 +282,11 @@ inline uint64_t harmonic_offset(uint64_t n, uint32_t H) {
 }
 constexpr int kMaxHarm = 16;
 
+// The argument checks every search entry point applies to one spectrum
+// (PULSCAN_OK, EINVAL or EUNSUPPORTED); *block gets the normalisation block.
+int check_search_args(const void *x, uint64_t n, int zmax, int chunk, const pulscan_opts &o,
+                      uint32_t *block);
+
 // Is width w of a 1..zmax bank searched under width_search?  The
 // logarithmic z sampling (section 4.1.3) searches z = w - 1 = 1, 2, 4, ...
 // and the largest drift, i.e. the widest width zmax itself.
