@@ -5,9 +5,9 @@
 //
 //  * Streaming.  A workgroup's range (a run of blocks of one or more series)
 //    is taken a batch of kStreamBatch blocks at a time, one block per wave.
-//    The next batch's loads are issued as soon as the current batch has
-//    arrived and are in flight (in registers) while it is normalised and
-//    searched.  Every issue is the same number of unconditional loads, so
+//    The next batch's loads are in flight (in registers) while the current
+//    one is normalised and searched, and the one after is requested as soon
+//    as a batch has been normalised (batch 1 only once batch 0 is in).  Every issue is the same number of unconditional loads, so
 //    that the compiler's wait counts never hold one batch for the next.  Normalised power goes to an LDS ring of blocks; a tile of
 //    blocks is searched once the ring holds every bin its windows reach
 //    (zmax - 1 bins past its end, `lag` blocks).
@@ -821,7 +821,9 @@ __device__ __forceinline__ Series series_at(const SpecDesc *descs, int s) {
 }
 
 // Four waves per SIMD (two workgroups per CU): at most 128 registers.
-template <int K, int EPL, bool FP>
+// PRUNE: the pruned search (the hot path), compiled without the dense
+// route and the table outputs; otherwise the dense search or the tables.
+template <int K, int EPL, bool FP, bool PRUNE>
 __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ Shared sh;
@@ -838,8 +840,6 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
   StageEntry *const pool = p.pool;
   uint32_t *const pool_head = p.pool_head;
   unsigned long long *const halo = p.halo;
-  float *const M_out = p.M;
-  uint32_t *const I_out = p.I;
   Ring<K> R;
   R.P = reinterpret_cast<float *>(lds);
   R.Sg = reinterpret_cast<float *>(lds + p.g.off_sg);
@@ -862,11 +862,11 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
   const uint32_t tag = *gp(p.gen) + 1u;
   const uint64_t units = p.total_blocks / p.align;
   const uint64_t g0 = units * wg / nwg * p.align, g1 = units * (wg + 1) / nwg * p.align;
-  const bool search = p.mode == kModeSearch;
-  const bool prune = search && !p.dense;
+  const bool search = PRUNE || p.mode == kModeSearch;
+  constexpr bool prune = PRUNE;
   NormOut no{};
-  no.P_out = p.mode == kModeTables ? p.P_out : nullptr;
-  no.stats_out = p.mode == kModeTables ? p.stats_out : nullptr;
+  no.P_out = !PRUNE && p.mode == kModeTables ? p.P_out : nullptr;
+  no.stats_out = !PRUNE && p.mode == kModeTables ? p.stats_out : nullptr;
   uint32_t wg_count = 0;  // candidates staged so far by this workgroup (uniform)
   uint32_t tc = 0;        // tiles banked so far (uniform)
   if (threadIdx.x == 0) {
@@ -908,9 +908,9 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     const bool consume = b < nbs;                // our last tile reaches into the next range
     const uint32_t zpub = min(lgs, b - a);
 
-    // this series' first thresholds, then the first two batches' loads
-    // (loads complete in order, so the thresholds can be stored before the
-    // spectrum arrives), then the set-up
+    // this series' first thresholds, then the first batch's loads (loads
+    // complete in order, so the thresholds can be stored before the spectrum
+    // arrives), then the set-up
     const float thr0 = threadIdx.x < zc ? gp(d.thr)[threadIdx.x] : 0.f;
     const uint32_t nbat = (b - a + NB - 1) / NB;
     Raw<EPL, FP> cur, nxt;
@@ -1007,7 +1007,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         for (uint32_t i = tid; i < nsl; i += nthr) slots[i] = 0ull;
         __syncthreads();
       }
-      if (prune) {
+      if constexpr (PRUNE) {
         // units (flagged lane, pass of 64 widths from its first flagged
         // width block), one per wave at a time; a lane's passes go to
         // consecutive waves
@@ -1102,8 +1102,8 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         for (uint32_t i = tid; i < nsl; i += nthr) {
           const unsigned long long key = slots[i];
           const size_t o = (size_t)chunk0 * zmax + i;
-          M_out[o] = key ? sunord((uint32_t)(key >> 32)) : -INFINITY;
-          I_out[o] = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : 0xFFFFFFFFu;
+          p.M[o] = key ? sunord((uint32_t)(key >> 32)) : -INFINITY;
+          p.I[o] = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : 0xFFFFFFFFu;
         }
       }
       __syncthreads();
@@ -1115,10 +1115,11 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     // f + NB - lag), and for the last batch up to b - lgs, so that the
     // halo's slots are free.  The halo step then normalises the first bins of
     // blocks b .. b+lgs-1 (wave w: block b + w) and banks up to b.  The next
-    // batch's loads (or the halo's) are issued once this batch's data are in,
-    // and are in flight while it is searched: the two register sets
-    // alternate.  (Issued together, two batches would arrive interleaved,
-    // the whole range at once, with nothing to search in the meantime.)
+    // batches' loads (or the halo's) are in flight while this one is
+    // searched: the two register sets alternate.  Only the first two batches
+    // are not requested together (issued together, they would arrive
+    // interleaved, every workgroup's whole first pair at once, with nothing
+    // to search in the meantime).
     auto step = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
       const uint32_t f = a + j * NB;
       const uint32_t k = f + wave;
@@ -1136,23 +1137,23 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         banked = t1;
       }
     };
-    // every load issued so far (the batch in r) has arrived
-    auto arrived = []() __attribute__((always_inline)) {
-      __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    };
+    // batch 1 is requested once batch 0 has arrived (every load issued so
+    // far); from then on batch j + 2 is requested as soon as batch j has been
+    // normalised, so that two batches are in flight while batch j + 1 is
+    // awaited
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    issue(1, nxt);
     uint32_t j = 0;
     while (true) {
-      arrived();
-      issue(j + 1, nxt);
       step(j, cur);
       if (j + 1 == nbat) break;  // the halo is in nxt
-      arrived();
       issue(j + 2, cur);
       step(j + 1, nxt);
       if (j + 2 == nbat) {  // the halo is in cur
         nxt = cur;
         break;
       }
+      issue(j + 3, nxt);
       j += 2;
     }
     {
@@ -1171,10 +1172,13 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
             // the next range's published statistics, or our own
             unsigned long long v = 0;
             bool ok = false;
-            if (lane < 4) {
+            // (the word's address from a fresh lane id, so that it is not
+            // computed at the kernel's start and kept live)
+            const uint32_t ln = ftid() & 63;
+            if (ln < 4) {
+              const unsigned long long *hwl = hw + 4 * wave + ln;
               for (uint32_t it = 0; it < spin; ++it) {
-                v = __hip_atomic_load(hw + 4 * wave + lane, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+                v = __hip_atomic_load(hwl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((uint32_t)(v >> 32) == tag) {
                   ok = true;
                   break;
@@ -1331,16 +1335,24 @@ bool choose_stream_geometry(uint32_t C, uint32_t B, uint32_t zmax_max, bool from
   return true;
 }
 
-template <int K, int EPL, bool FP>
+template <int K, int EPL, bool FP, bool PRUNE>
 static const void *stream_fn() {
-  return reinterpret_cast<const void *>(&stream_kernel<K, EPL, FP>);
+  return reinterpret_cast<const void *>(&stream_kernel<K, EPL, FP, PRUNE>);
 }
 
-static const void *stream_entry(const StreamGeometry &g, bool fp) {
-  if (g.K == 16 && g.EPL == 16) return fp ? stream_fn<16, 16, true>() : stream_fn<16, 16, false>();
-  if (g.K == 4 && g.EPL == 16) return fp ? stream_fn<4, 16, true>() : stream_fn<4, 16, false>();
-  if (g.K == 4 && g.EPL == 4) return fp ? stream_fn<4, 4, true>() : stream_fn<4, 4, false>();
+template <bool PRUNE>
+static const void *stream_entry_p(const StreamGeometry &g, bool fp) {
+  if (g.K == 16 && g.EPL == 16)
+    return fp ? stream_fn<16, 16, true, PRUNE>() : stream_fn<16, 16, false, PRUNE>();
+  if (g.K == 4 && g.EPL == 16)
+    return fp ? stream_fn<4, 16, true, PRUNE>() : stream_fn<4, 16, false, PRUNE>();
+  if (g.K == 4 && g.EPL == 4)
+    return fp ? stream_fn<4, 4, true, PRUNE>() : stream_fn<4, 4, false, PRUNE>();
   return nullptr;
+}
+
+static const void *stream_entry(const StreamGeometry &g, bool fp, bool prune) {
+  return prune ? stream_entry_p<true>(g, fp) : stream_entry_p<false>(g, fp);
 }
 
 // Workgroups above 64 KiB of LDS must say so before they launch.
@@ -1354,20 +1366,28 @@ static bool allow_lds(const void *fn, size_t bytes) {
   return true;
 }
 
+// Every workgroup of a launch must be resident at once (workgroups wait for
+// their neighbours' words), so the occupancy is the smaller of the two
+// instantiations'.
 int stream_occupancy(const StreamGeometry &g, bool from_power) {
-  const void *fn = stream_entry(g, from_power);
-  if (!fn || !allow_lds(fn, g.lds_bytes)) return 0;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kStreamThreads, g.lds_bytes) !=
-      hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
+  int occ = 1 << 30;
+  for (int pr = 0; pr < 2; ++pr) {
+    const void *fn = stream_entry(g, from_power, pr != 0);
+    if (!fn || !allow_lds(fn, g.lds_bytes)) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kStreamThreads, g.lds_bytes) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    occ = nb < occ ? nb : occ;
   }
-  return nb;
+  return occ;
 }
 
 hipError_t launch_stream(const StreamParams &p, hipStream_t stream) {
-  const void *fn = stream_entry(p.g, p.from_power != 0);
+  const bool prune = p.mode == kModeSearch && !p.dense;
+  const void *fn = stream_entry(p.g, p.from_power != 0, prune);
   if (!fn || !allow_lds(fn, p.g.lds_bytes)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StreamParams *>(&p)};
   return hipLaunchKernel(fn, dim3(p.nwg), dim3(kStreamThreads), args, p.g.lds_bytes, stream);
