@@ -255,10 +255,12 @@ int pulscan_ctx_set_kernel(pulscan_ctx *ctx, int kernel);
 int pulscan_ctx_last_kernel(pulscan_ctx *ctx, int *kernel);
 
 /* Polls of a word another workgroup publishes (a count, or the statistics of
- * a halo block) before the streaming kernel gives up on it: a lost count
- * makes the search return PULSCAN_EHIP, a lost statistics word is recomputed
- * from the spectrum.  Default 2^20 (a hundred milliseconds or more); a small
- * value forces the give-up paths in tests.  polls >= 1, else EINVAL. */
+ * a halo block) before a bank kernel gives up on it: a lost count makes the
+ * search return PULSCAN_EHIP (and the context re-arms its counters before
+ * its next launch), a lost statistics word (streaming kernel) is recomputed
+ * from the spectrum.  Every kernel still runs to its end.  Default 2^20 (a
+ * hundred milliseconds or more); a small value forces the give-up paths in
+ * tests.  polls >= 1, else EINVAL. */
 int pulscan_ctx_set_spin(pulscan_ctx *ctx, uint32_t polls);
 
 /* The single-spectrum search of pulscan_search_ex for callers that cannot

@@ -573,6 +573,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     bp.total2 = fin ? nullptr : reinterpret_cast<unsigned long long *>(a.out->count_device);
     bp.overflow = &cnt->overflow;
     bp.scan_in_kernel = tiles <= kInKernelScanMax ? 1 : 0;
+    bp.spin = ctx->spin;
     if (!sk && !bp.scan_in_kernel) {
       const uint64_t nspan = (tiles + kScanSpan - 1) / kScanSpan;
       st = grow(ctx, ctx->span_sum, nspan * sizeof(uint32_t), false);
@@ -736,7 +737,14 @@ int finish(pulscan_ctx *ctx, const RunArgs &a, const Pending &pd) {
   Counters hc{};
   HIP_TRY(hipMemcpyAsync(&hc, pd.cnt, sizeof(hc), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  if (hc.overflow == 2) return PULSCAN_EHIP;  // a tile's count never arrived
+  if (hc.overflow == 2) {
+    // a count never arrived: its workgroup may have reserved pool entries or
+    // published its word after the scan re-armed them, so the next launch
+    // clears the counters first (directly, not from a captured graph)
+    ctx->counts_dirty = true;
+    drop_graph(ctx);
+    return PULSCAN_EHIP;
+  }
   if (hc.overflow) return PULSCAN_ENOMEM;
   const unsigned long long total = pd.best ? hc.best : hc.total;
   out->count = total;

@@ -673,11 +673,9 @@ __device__ __forceinline__ void eval_unit(const PT *__restrict__ Pl,
 // run of tiles, the run totals are scanned across the workgroup, and each
 // thread writes its run's prefixes.  Also records the total and the staging
 // overflow, and re-arms the pool head for the next launch.
-constexpr uint32_t kWordSpin = 1u << 22;  // polls per word before giving up
-
 __device__ __forceinline__ uint32_t tile_count_of(const BankParams &p, uint64_t i, bool &lost) {
   unsigned long long v = 0;
-  for (uint32_t k = 0; k < kWordSpin; ++k) {
+  for (uint32_t k = 0; k < p.spin; ++k) {  // p.spin polls per word before giving up
     v = __hip_atomic_load(p.tile_word + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (v & kTilePublished) return (uint32_t)v;
     __builtin_amdgcn_s_sleep(1);

@@ -86,6 +86,7 @@ struct BankParams {
   unsigned long long *total2;  // optional second destination (the caller's)
   uint32_t *overflow;      // 1: the pool was too small; 2: a tile's count never arrived
   int scan_in_kernel;      // 1: the last tile scans the counts; 0: launch_scan_big does
+  uint32_t spin;           // polls of a tile's count word before the scan gives up on it
   float *M;                // tables mode: nchunks x zmax (spectrum 0 only)
   uint32_t *I;
   float *P_out;            // tables mode, optional: normalised power
