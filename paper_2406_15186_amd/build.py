@@ -13,13 +13,16 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libpulscan.so")
 SOURCES = ["api.hip", "bank.hip", "stream.hip", "signif.hip", "harmonic.hip", "serve.hip",
            "noalloc.hip"]
-# Per-translation-unit flags.  stream.hip: built without NaN semantics (its
-# inputs are finite), so that the compiler may fold cross-lane moves into DPP
-# min/max instructions; and without the atomic optimizer, which would turn
+# Per-translation-unit flags.  stream.hip and bank.hip: built without NaN
+# semantics (their inputs are finite), so that the compiler may fold
+# cross-lane moves into DPP min/max instructions and a minimum or maximum of
+# three values into one instruction.  stream.hip also without the atomic
+# optimizer, which would turn
 # each LDS atomic whose address is the same in every lane into a loop over
 # the active lanes (one v_readlane and a scalar compare per lane) where the
 # LDS itself serialises the lanes in a few cycles.
-EXTRA = {"stream.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+EXTRA = {"stream.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+         "bank.hip": ["-fno-honor-nans"]}
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -32,6 +32,7 @@
 #include <float.h>
 
 #include "internal.hpp"
+#include "mom.hpp"
 
 namespace pulscan {
 
@@ -66,28 +67,6 @@ __device__ __forceinline__ SpecDesc load_desc(const SpecDesc *p) {
 template <int K>
 __host__ __device__ constexpr int pitch_of() {
   return K == 1 ? 64 : 64 + 64 / K;
-}
-
-// Twice the median of four values, i.e. the sum of the middle two.  With m
-// the median of a, b, c and lo, hi their minimum and maximum, adding d
-// leaves {m, median(lo, d, hi)} as the middle pair, so the result is one
-// rounding of the sum of the same two values however they are picked.
-// Carrying the factor 2 through the tree and removing it with one exact
-// power-of-two scale at the end rounds exactly as halving at every level
-// would.  Inputs are finite.
-__device__ __forceinline__ float m4x2(float a, float b, float c, float d) {
-  const float m = __builtin_amdgcn_fmed3f(a, b, c);
-  const float lo = fminf(fminf(a, b), c), hi = fmaxf(fmaxf(a, b), c);
-  return m + __builtin_amdgcn_fmed3f(lo, d, hi);
-}
-// The same for values just loaded from memory: min and max as medians with
-// an infinite third operand, which the compiler does not precede with a
-// quieting of signalling NaNs as it does for fminf / fmaxf of loaded values.
-__device__ __forceinline__ float m4x2_ld(float a, float b, float c, float d) {
-  const float m = __builtin_amdgcn_fmed3f(a, b, c);
-  const float lo = __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, b, -INFINITY), c, -INFINITY);
-  const float hi = __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, b, INFINITY), c, INFINITY);
-  return m + __builtin_amdgcn_fmed3f(lo, d, hi);
 }
 
 // Lane l of each row of 16 receives lane l + k's value (row_shl k); lanes
@@ -130,8 +109,8 @@ __device__ __forceinline__ void wave_mom2(float (&a)[EPL], float (&b)[EPL], floa
 #pragma unroll
     for (int m = 0; m < q; ++m) {
       if (cnt == EPL) {  // the inputs themselves (or their deviations)
-        a[m] = m4x2_ld(a[m], a[m + q], a[m + 2 * q], a[m + 3 * q]);
-        b[m] = m4x2_ld(b[m], b[m + q], b[m + 2 * q], b[m + 3 * q]);
+        a[m] = m4x2(a[m], a[m + q], a[m + 2 * q], a[m + 3 * q]);
+        b[m] = m4x2(b[m], b[m + q], b[m + 2 * q], b[m + 3 * q]);
       } else {
         a[m] = m4x2(a[m], a[m + q], a[m + 2 * q], a[m + 3 * q]);
         b[m] = m4x2(b[m], b[m + q], b[m + 2 * q], b[m + 3 * q]);
@@ -170,7 +149,7 @@ __device__ __forceinline__ float wave_mom1(const float (&a)[EPL], float c) {
     float e[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) e[j] = DEV ? fabsf(a[m + j * Q] - c) : a[m + j * Q];
-    v[m] = DEV ? m4x2(e[0], e[1], e[2], e[3]) : m4x2_ld(e[0], e[1], e[2], e[3]);
+    v[m] = DEV ? m4x2(e[0], e[1], e[2], e[3]) : m4x2(e[0], e[1], e[2], e[3]);
   }
 #pragma unroll
   for (int cnt = Q; cnt >= 4; cnt /= 4) {
@@ -350,6 +329,13 @@ __device__ __forceinline__ void normalise_block(BlockData<EPL> &bd, uint32_t b, 
     med_im = wave_median_exact<EPL, false>(im, 0.f);
     mad_re = wave_median_exact<EPL, true>(re, med_re);
     mad_im = wave_median_exact<EPL, true>(im, med_im);
+  } else if constexpr (EPL == 4 || EPL == 16) {
+    // the statistics of the streaming kernel, in the same operations
+    const BlockStats st = block_stats<EPL>(re, im, lane);
+    med_re = st.med_re;
+    med_im = st.med_im;
+    mad_re = st.mad_re;
+    mad_im = st.mad_im;
   } else if constexpr (EPL >= 16) {
     med_re = wave_mom1<EPL, false>(re, 0.f);
     med_im = wave_mom1<EPL, false>(im, 0.f);
