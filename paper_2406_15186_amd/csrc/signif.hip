@@ -128,16 +128,18 @@ __device__ __forceinline__ double sigma_from_logp(double L) {
                     1.0));
     }
   }
-  // Halley's iteration converges cubically: from the start's 1e-4 relative
-  // error at s near 6, two steps; a relative step of 1e-10 ends it (the
-  // result is reported in FP32)
+  // Halley's iteration converges cubically: a step of at most 1e-4 (relative
+  // to max(1, s)) leaves an error of order 1e-12, so it ends the iteration.
+  // From the start's error (below 5e-5 relative for L <= -20, i.e. s >= 6)
+  // that is the first step; closer to the body of the distribution a few
+  // more (the result is reported in FP32).
   for (int it = 0; it < 200; ++it) {
     double f, df;
     log_norm_sf_d(s, f, df);
     const double g = f - L, d2 = df * (-df - s);
     const double step = 2.0 * g * df / (2.0 * df * df - g * d2);
     s -= step;
-    if (fabs(step) <= 1e-10 * fmax(1.0, fabs(s))) break;
+    if (fabs(step) <= 1e-4 * fmax(1.0, fabs(s))) break;
   }
   return s;
 }
