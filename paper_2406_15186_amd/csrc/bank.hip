@@ -571,11 +571,15 @@ __device__ __forceinline__ uint32_t bound_lane(const PT *__restrict__ Pl,
     if ((u + 1) % S == 0) hit |= U >= t1[u / S];
   }
   uint32_t fl = hit ? 0u : nblk;
-  U = Sg[own] + Sg[own + 1];
-  // blocks are taken kBoundBatch at a time with their loads issued together
-  // (indices clamped to the last block, whose terms are then not used)
+  if (__ballot(fl == nblk) == 0ull) return fl;  // every lane already flagged
+  // Whether any later block reaches its threshold: the largest U - Tb[b]
+  // (U >= Tb[b] exactly when U - Tb[b] >= 0).  Blocks are taken kBoundBatch
+  // at a time with their loads issued together (indices clamped to the last
+  // block, whose terms are then not used).
+  const float U1 = Sg[own] + Sg[own + 1];
+  U = U1;
+  float m = -INFINITY;
   for (uint32_t b = 1; b < nblk; b += kBoundBatch) {
-    if (__ballot(fl == nblk) == 0ull) break;  // every lane already flagged
     float sg[kBoundBatch], tb[kBoundBatch];
 #pragma unroll
     for (int k = 0; k < kBoundBatch; ++k) {
@@ -587,7 +591,27 @@ __device__ __forceinline__ uint32_t bound_lane(const PT *__restrict__ Pl,
     for (int k = 0; k < kBoundBatch; ++k) {
       if (b + k < nblk) {
         U += sg[k];
-        if (fl == nblk && U >= tb[k]) fl = b + k;
+        m = fmaxf(m, U - tb[k]);
+      }
+    }
+  }
+  if (fl == nblk && m >= 0.f) {
+    // the first such block: the same sums in the same order
+    U = U1;
+    for (uint32_t b = 1; b < nblk && fl == nblk; b += kBoundBatch) {
+      float sg[kBoundBatch], tb[kBoundBatch];
+#pragma unroll
+      for (int k = 0; k < kBoundBatch; ++k) {
+        const uint32_t bb = min(b + k, nblk - 1);
+        sg[k] = Sg[own + bb + 1];
+        tb[k] = Tb[bb];
+      }
+#pragma unroll
+      for (int k = 0; k < kBoundBatch; ++k) {
+        if (b + k < nblk) {
+          U += sg[k];
+          if (fl == nblk && U >= tb[k]) fl = b + k;
+        }
       }
     }
   }
