@@ -42,8 +42,8 @@ BANK_OPS_PER_BIN_WIDTH = 1.5
 # the one the counters were taken on)
 KERNEL_NAMES = {0: "stream_kernel", 1: "bank_kernel"}   # PULSCAN_KERNEL_STREAM / _TILED
 TRAFFIC = {
-    "stream_kernel": ("stream_kernel_plain_2e23_traffic.json", "stream.hip"),
-    "bank_kernel": ("bank_kernel_plain_2e23_traffic.json", "bank.hip"),
+    "stream_kernel": ("stream_kernel_plain_2e23_traffic.json", ("stream.hip", "mom.hpp")),
+    "bank_kernel": ("bank_kernel_plain_2e23_traffic.json", ("bank.hip", "mom.hpp")),
 }
 
 TIMING_EVERY = 16           # bank launches per timed one (each timed launch costs ~5 us of step)
@@ -59,17 +59,25 @@ def measured_traffic(kname):
     """HBM bytes per launch of bank kernel `kname` from its committed counter
     summary, or None when there is none or the kernel's source has changed
     since the counters were taken."""
-    import hashlib
-    fname, source = TRAFFIC[kname]
+    fname, sources = TRAFFIC[kname]
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", fname)))
     except (OSError, ValueError):
         return None
-    src = hashlib.sha256(open(os.path.join(ROOT, "paper_2406_15186_amd", "csrc", source),
-                              "rb").read()).hexdigest()
-    if rec.get("bank_source_sha256") != src:
+    if rec.get("source_sha256") != source_digest(sources):
         return None
     return int(rec["bytes_per_launch"])
+
+
+def source_digest(sources):
+    """SHA-256 over the kernel's source files, in order (the key of a counter
+    summary)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(ROOT, "paper_2406_15186_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(*a):
