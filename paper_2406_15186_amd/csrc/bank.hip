@@ -949,6 +949,13 @@ __global__ __launch_bounds__(threads_for<EPL>(), (waves_per_eu_for<EPL, EXACT>()
         for (uint32_t i = tid; i < chunks_per_tile * zmax; i += nthr) slots[i] = 0ull;
         __syncthreads();
       }
+    }
+    // With more than a quarter of its lanes flagged (a power series of many
+    // degrees of freedom per bin, such as a harmonic stage, whose thresholds
+    // sit close to its mean: the union windows reach them everywhere) the
+    // tile takes the dense route, which evaluates every lane in the same
+    // canonical order faster than per-lane work units.
+    if (prune && n_items * 4u <= T / K) {
       // work units (flagged lane, width block, half of the lane's starts).
       // The (lane, block) pairs are lane-major, so that the lanes of a wave
       // share lanes' chunks but not widths and their slot merges rarely
