@@ -490,6 +490,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=3)
     ap.add_argument("--cpu-single-bins", type=int, default=1 << 20)
+    ap.add_argument("--numharm", type=int, default=1,
+                    help="harmonic stages searched by the timed leg (1: the power only); the "
+                         "throughput then counts every stage's bin-widths")
     ap.add_argument("--dense", action="store_true",
                     help="evaluate every width block (no pruning bound): same candidates")
     ap.add_argument("--kernel", choices=("auto", "stream", "tiled"), default="auto",
@@ -536,25 +539,28 @@ def main():
     d = torch.from_numpy(x).to("cuda:0")
     stream = torch.cuda.current_stream()
 
+    nh = max(args.numharm, 1)
     ms_per_step, gpu_ms, bank_ms, ref_count = timed_steps(
-        ctx, pk, d, Z, C, sigma, stream, args.steps, args.warmup, dense=args.dense)
-    value = n * Z / (ms_per_step * 1e-3) / 1e9
+        ctx, pk, d, Z, C, sigma, stream, args.steps, args.warmup, dense=args.dense, numharm=nh)
+    stage_bins = sum(n // H for H in range(1, nh + 1))
+    value = stage_bins * Z / (ms_per_step * 1e-3) / 1e9
     kname = KERNEL_NAMES[ctx.pulscan_ctx_last_kernel()]
     log(f"bench: {ref_count} candidates per step; {ms_per_step:.4f} ms/step wall, "
         f"{gpu_ms:.4f} ms/step GPU, bank kernel ({kname}) {bank_ms * 1e3:.1f} us")
 
     # synchronous single calls: per-call latency including the host round trip
-    cap = ((n + C - 1) // C) * Z
+    cap = sum(((n // H) + C - 1) // C for H in range(1, nh + 1)) * Z
     lat = []
     for _ in range(args.latency_calls):
         torch.cuda.synchronize()
         a = time.perf_counter()
-        ctx.pulscan_search_ex(d, Z, C, sigma, capacity=cap, opts=pk.make_opts(dense=args.dense))
+        ctx.pulscan_search_ex(d, Z, C, sigma, capacity=cap,
+                              opts=pk.make_opts(dense=args.dense, numharm=nh))
         lat.append((time.perf_counter() - a) * 1e3)
     lat = lat or [0.0]
 
     variants = None
-    if not args.no_variants and not args.dense:
+    if not args.no_variants and not args.dense and nh == 1:
         variants = {
             "log_z": variant_leg(ctx, pk, d, wl, stream, args, ms_per_step, "log-z widths",
                                  width_search=pk.PULSCAN_W_LOG2),
@@ -635,7 +641,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "nbins": n, "zmax": Z, "chunk": C, "sigma": sigma,
                    "tones": len(tones), "red_frac": wl.red_frac,
-                   "path": "plain, async, " + ("dense" if args.dense else "pruned"),
+                   "path": "plain, async, " + ("dense" if args.dense else "pruned")
+                           + (f", {nh} harmonic stages (the bank kernel figure averages the "
+                              "power pass and the stage search)" if nh > 1 else ""),
                    "kernel": args.kernel},
         "roofline": roofline,
         "cpu_baseline": cpu,
