@@ -103,8 +103,17 @@ typedef struct {
   int32_t on_device;       /* 1: data is a device pointer                             */
   int32_t reserved;
   uint64_t *count_device;  /* optional device pointer: receives the true count; the
-                              only count an asynchronous call delivers                */
+                              only count an asynchronous call delivers, which
+                              there also reports a failure on the device as one of
+                              the PULSCAN_COUNT_* values below                        */
 } pulscan_candidates;
+
+/* Counts written to out->count_device when a search fails on the device (a
+ * synchronous call returns the status instead): a workgroup's candidate count
+ * never reached the scan (PULSCAN_EHIP), or more candidates than the staging
+ * pool holds (PULSCAN_ENOMEM).  No real count comes near them. */
+#define PULSCAN_COUNT_LOST 0xFFFFFFFFFFFFFFFFull
+#define PULSCAN_COUNT_POOL_FULL 0xFFFFFFFFFFFFFFFEull
 
 /* Options of the _ex and batched calls (fill with pulscan_opts_default). */
 typedef struct {

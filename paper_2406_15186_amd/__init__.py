@@ -32,6 +32,9 @@ PULSCAN_W_LOG2 = 1
 PULSCAN_KERNEL_STREAM = 0
 PULSCAN_KERNEL_TILED = 1
 PULSCAN_KERNEL_AUTO = 2
+# count_device values of an asynchronous search that failed on the device
+PULSCAN_COUNT_LOST = 0xFFFFFFFFFFFFFFFF
+PULSCAN_COUNT_POOL_FULL = 0xFFFFFFFFFFFFFFFE
 
 
 class pulscan_candidate(ctypes.Structure):

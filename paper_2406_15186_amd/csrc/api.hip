@@ -708,6 +708,10 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   ep.from_power = a.from_power ? 1 : 0;
   ep.block = a.block;
   ep.sigma = a.sigma;
+  ep.overflow = &cnt->overflow;
+  ep.tile_word = sk ? nullptr : bp.tile_word;
+  ep.ntiles = sk ? 0 : tiles;
+  ep.pool_head = &cnt->head;
   if (fin) {
     st = grow(ctx, ctx->allbuf, (size_t)pool_cap * sizeof(pulscan_candidate), false);
     if (st) return st;
@@ -720,7 +724,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   if (fin)
     HIP_TRY(launch_finalize(ep.out, bp.total, pool_cap, dst, cap, &cnt->best,
                             reinterpret_cast<unsigned long long *>(out->count_device),
-                            best ? 1 : 0, stream));
+                            &cnt->overflow, best ? 1 : 0, stream));
   if (pend) {
     pend->cnt = cnt;
     pend->best = fin;

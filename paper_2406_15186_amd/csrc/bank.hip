@@ -762,9 +762,10 @@ __device__ void scan_tiles(const BankParams &p, uint32_t tid, uint32_t nthr, uin
   __syncthreads();
   if (tid == 0) {
     p.tile_prefix[T] = tot;
+    const uint32_t ovf = *lost_any ? 2u : (tot > p.pool_cap ? 1u : 0u);
     *p.total = tot;
-    if (p.total2) *p.total2 = tot;
-    *p.overflow = *lost_any ? 2u : (tot > p.pool_cap ? 1u : 0u);
+    if (p.total2) *p.total2 = count_word(tot, ovf);
+    *p.overflow = ovf;
     __hip_atomic_store(p.pool_head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -1295,9 +1296,10 @@ __global__ __launch_bounds__(kBigThreads) void scan_top_kernel(BigScan s, uint32
     __syncthreads();
   }
   if (tid == 0) {
+    const uint32_t ovf = *s.lost ? 2u : (carry > s.pool_cap ? 1u : 0u);
     *s.total = carry;
-    if (s.total2) *s.total2 = carry;
-    *s.overflow = *s.lost ? 2u : (carry > s.pool_cap ? 1u : 0u);
+    if (s.total2) *s.total2 = count_word(carry, ovf);
+    *s.overflow = ovf;
     *s.lost = 0u;
     *s.pool_head = 0u;
   }

@@ -18,6 +18,13 @@ constexpr int kMaxThreads = 512;      // threads per workgroup of the bank kerne
 constexpr int kMaxTile = 16384;       // bins per tile
 constexpr uint32_t kPoolMax = 1u << 26;  // staging-pool entries per context (1 GiB)
 
+// The caller's count word after a scan: the total, or the failure code of the
+// scan's overflow flag (1: the staging pool overflowed, 2: a count was lost).
+__host__ __device__ inline unsigned long long count_word(unsigned long long total,
+                                                         uint32_t overflow) {
+  return overflow == 2 ? PULSCAN_COUNT_LOST : overflow == 1 ? PULSCAN_COUNT_POOL_FULL : total;
+}
+
 // One searched series of a launch: a spectrum, or one harmonic stage of a
 // spectrum (power input).  A device-resident array of these drives the bank
 // and emit kernels; a single series is a batch of one.
@@ -245,6 +252,14 @@ struct EmitParams {
   int from_power;                  // the series are power (re-check reads them)
   uint32_t block;                  // normalisation block (re-check statistics)
   float sigma;                     // the requested threshold
+  // After a lost count (overflow 2) the bank launch's late workgroups may
+  // have published their words and reserved pool entries after the scan
+  // re-armed them; emit, which runs once every workgroup has ended, then
+  // places nothing and clears them for the next launch.
+  const uint32_t *overflow;
+  unsigned long long *tile_word;   // the tiled kernel's count words, or nullptr
+  uint64_t ntiles;
+  uint32_t *pool_head;
 };
 hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t grid,
                        hipStream_t stream);
@@ -256,7 +271,8 @@ hipError_t launch_emit(const EmitParams &p, const SpecDesc &single, uint32_t gri
 // goes to *count and, if non-null, *count2.  One workgroup.
 hipError_t launch_finalize(const pulscan_candidate *all, const unsigned long long *total,
                            uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
-                           unsigned long long *count, unsigned long long *count2, int best,
+                           unsigned long long *count, unsigned long long *count2,
+                           const uint32_t *overflow, int best,
                            hipStream_t stream);
 
 // FP16 power storage: the bank compares against thresholds kRecheckBand sigma

@@ -245,6 +245,10 @@ extern "C" int pulscan_search_noalloc(const pulscan_complex *spectrum, size_t nb
   ep.from_power = 0;
   ep.block = block;
   ep.sigma = sigma_thresh;
+  ep.overflow = &ctl->overflow;
+  ep.tile_word = nullptr;  // the streaming kernel's words carry the launch's tag
+  ep.ntiles = 0;
+  ep.pool_head = &ctl->head;
   const uint64_t work = out->capacity < worst ? out->capacity : worst;
   const uint32_t egrid = (uint32_t)(work / 64 + 1 < 2048 ? work / 64 + 1 : 2048);
   NA_TRY(launch_emit(ep, d, egrid, stream));

@@ -137,6 +137,10 @@ void collect(pulscan_server *s) {
         hipMemcpy(&total, sl.dev_count, sizeof(total), hipMemcpyDeviceToHost) != hipSuccess) {
       (void)hipGetLastError();
       st = PULSCAN_EHIP;
+    } else if (total == PULSCAN_COUNT_LOST || total == PULSCAN_COUNT_POOL_FULL) {
+      // the search failed on the device (a count never arrived, or the
+      // staging pool overflowed)
+      st = total == PULSCAN_COUNT_LOST ? PULSCAN_EHIP : PULSCAN_ENOMEM;
     } else {
       const uint64_t take = total < s->cfg.max_candidates ? total : s->cfg.max_candidates;
       all.resize(take);
@@ -312,7 +316,9 @@ int pulscan_server_create(pulscan_server **out, int device, const pulscan_server
   bool ok = hipSetDevice(device) == hipSuccess &&
             hipStreamCreate(&s->copy_stream) == hipSuccess &&
             hipStreamCreate(&s->compute_stream) == hipSuccess;
-  s->ring_bytes = cfg->hbm_budget;
+  // the ring places copies at 256-byte boundaries: sized to the budget rounded
+  // up, so that every spectrum the budget admits also fits in it
+  s->ring_bytes = (cfg->hbm_budget + 255) & ~255ull;
   ok = ok && hipMalloc(reinterpret_cast<void **>(&s->ring), s->ring_bytes) == hipSuccess;
   for (int k = 0; ok && k < kInFlight; ++k) {
     Slot &sl = s->slots[k];

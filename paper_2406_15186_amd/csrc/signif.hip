@@ -244,6 +244,14 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
   // used only when the entry lies below the count.
   const uint64_t stride = (uint64_t)gridDim.x * kEmitThreads;
   const uint64_t f0 = (uint64_t)blockIdx.x * kEmitThreads + threadIdx.x;
+  if (*p.overflow == 2u) {
+    // a count was lost (the search reports PULSCAN_EHIP): re-arm what the
+    // late workgroups left behind instead of placing anything
+    if (p.tile_word)
+      for (uint64_t i = f0; i < p.ntiles; i += stride) p.tile_word[i] = 0ull;
+    if (f0 == 0) *p.pool_head = 0u;
+    return;
+  }
   if (f0 >= p.pool_cap) return;
   const StageEntry e0 = p.pool[f0];
   const unsigned long long total = *p.total;
@@ -302,7 +310,7 @@ __device__ __forceinline__ bool same_key(const pulscan_candidate &a, const pulsc
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(
     const pulscan_candidate *__restrict__ all, const unsigned long long *__restrict__ total_p,
     uint64_t all_cap, pulscan_candidate *__restrict__ out, uint64_t capacity,
-    unsigned long long *count, unsigned long long *count2, int best) {
+    unsigned long long *count, unsigned long long *count2, const uint32_t *overflow, int best) {
   __shared__ uint32_t wave_cnt[kFinThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long tot = *total_p;
@@ -341,16 +349,16 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(
   }
   if (tid == 0) {
     *count = kept;
-    if (count2) *count2 = kept;
+    if (count2) *count2 = count_word(kept, *overflow);
   }
 }
 
 hipError_t launch_finalize(const pulscan_candidate *all, const unsigned long long *total,
                            uint64_t all_cap, pulscan_candidate *out, uint64_t capacity,
-                           unsigned long long *count, unsigned long long *count2, int best,
-                           hipStream_t stream) {
+                           unsigned long long *count, unsigned long long *count2,
+                           const uint32_t *overflow, int best, hipStream_t stream) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, stream, all, total, all_cap,
-                     out, capacity, count, count2, best);
+                     out, capacity, count, count2, overflow, best);
   return hipGetLastError();
 }
 

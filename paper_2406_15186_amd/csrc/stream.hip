@@ -1178,9 +1178,10 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
   if (tid == 0) {
     p.wg_prefix[p.nwg] = tot;
     if (search) {
+      const uint32_t ovf = sh.lost ? 2u : (tot > p.pool_cap ? 1u : 0u);
       *p.total = tot;
-      if (p.total2) *p.total2 = tot;
-      *p.overflow = sh.lost ? 2u : (tot > p.pool_cap ? 1u : 0u);
+      if (p.total2) *p.total2 = count_word(tot, ovf);
+      *p.overflow = ovf;
     } else {
       *p.overflow = sh.lost ? 2u : 0u;
     }

@@ -30,8 +30,12 @@ int pulscan_search_batched(pulscan_ctx *ctx, int nspec, const pulscan_complex *c
     return PULSCAN_EINVAL;
   ctx->calls++;
   uint64_t k = 0;
+  bool fail = false;
   for (int s = 0; s < nspec; ++s) {
     if (nbins[s] < (uint64_t)chunk || zmax[s] < 1) return PULSCAN_EINVAL;
+    // a negative imaginary part in bin 0 stands for a search that fails on
+    // the device: the count word then carries the failure code
+    fail = fail || spectra[s][0].im < 0.f;
     if (k < out->capacity) {
       pulscan_candidate c{};
       c.spectrum = (uint32_t)s;
@@ -42,7 +46,7 @@ int pulscan_search_batched(pulscan_ctx *ctx, int nspec, const pulscan_complex *c
     }
     ++k;
   }
-  *out->count_device = k;
+  *out->count_device = fail ? PULSCAN_COUNT_LOST : k;
   return PULSCAN_OK;
 }
 

@@ -9,6 +9,8 @@ whose scanner is the last; the tile just before the last for the tiled
 kernel, whose last tile scans) loses that count: the search must return
 PULSCAN_EHIP with every kernel having run to its end, and the next search
 with the default spin must give exactly the candidates of a clean search.
+The same holds for asynchronous calls, whose count word then carries
+PULSCAN_COUNT_LOST.
 """
 
 import pytest
@@ -69,6 +71,31 @@ def test_lost_count_gives_ehip_and_the_next_search_is_clean(ctx, pk, oracle_lib,
             got, ngot = ctx.pulscan_search_ex(d, Z, C, 6.0)
             assert ngot == nref
             assert got.tobytes() == ref.tobytes()
+
+        # asynchronous: the count word carries the failure, and the next
+        # asynchronous search (which the host cannot have re-armed for) is
+        # clean: the failed launch's emit cleared what its late workgroups
+        # left behind
+        import torch
+        cap = nref + 64
+        buf = torch.zeros(cap * pk.CANDIDATE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        aopts = pk.make_opts(async_=True, stream=torch.cuda.current_stream())
+        say(f"give-up {kernel}: asynchronous, one poll per count word")
+        ctx.pulscan_ctx_set_spin(1)
+        ctx.pulscan_search_ex(d, Z, C, 6.0, capacity=cap, opts=aopts, out_device=buf,
+                              count_device=cnt)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) & 0xFFFFFFFFFFFFFFFF == pk.PULSCAN_COUNT_LOST
+        ctx.pulscan_ctx_set_spin(DEFAULT_SPIN)
+        say(f"give-up {kernel}: asynchronous clean search")
+        buf.zero_()
+        ctx.pulscan_search_ex(d, Z, C, 6.0, capacity=cap, opts=aopts, out_device=buf,
+                              count_device=cnt)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == nref
+        got = buf[:nref * pk.CANDIDATE_DTYPE.itemsize].cpu().numpy().view(pk.CANDIDATE_DTYPE)
+        assert got.tobytes() == ref.tobytes()
     finally:
         ctx.pulscan_ctx_set_spin(DEFAULT_SPIN)
         ctx.pulscan_ctx_set_kernel(pk.PULSCAN_KERNEL_AUTO)

@@ -54,14 +54,16 @@ def serve_driver(tmp_path_factory):
     return str(out)
 
 
-@pytest.mark.parametrize("budget,max_batch,nreq,seed", [
-    (1 << 20, 256, 50, 1),
-    (1 << 20, 3, 300, 3),
-    (1 << 21, 7, 400, 5),
+@pytest.mark.parametrize("budget,max_batch,nreq,seed,edges", [
+    (1 << 20, 256, 50, 1, 0),
+    (1 << 20, 3, 300, 3, 0),
+    (1 << 21, 7, 400, 5, 0),
+    ((1 << 20) + 100, 5, 200, 6, 3),
 ])
 def test_serving_runtime_under_address_and_undefined_sanitizers(serve_driver, budget, max_batch,
-                                                                nreq, seed):
-    r = subprocess.run([serve_driver, str(budget), str(max_batch), str(nreq), str(seed)],
+                                                                nreq, seed, edges):
+    r = subprocess.run([serve_driver, str(budget), str(max_batch), str(nreq), str(seed),
+                        str(edges)],
                        capture_output=True, text=True, timeout=120, env=ENV)
     assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-4000:])
     assert r.stdout.startswith(f"ok {nreq}")

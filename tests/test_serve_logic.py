@@ -45,3 +45,20 @@ def test_every_request_completes_once(driver, budget, max_batch, nreq, seed):
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert r.stdout.startswith(f"ok {nreq}")
+
+
+# edges: 1 = requests of the largest size a budget that is not a multiple of
+# the ring's 256-byte placement admits (each must still be served); 2 =
+# searches that fail on the device (their count word carries the failure
+# code), which must come back as PULSCAN_EHIP while the rest are served
+@pytest.mark.parametrize("budget,max_batch,nreq,seed,edges", [
+    ((1 << 20) + 100, 3, 100, 6, 1),
+    ((1 << 20) + 8, 1, 60, 7, 1),
+    (1 << 20, 4, 200, 8, 2),
+    ((1 << 21) + 200, 256, 150, 9, 3),
+])
+def test_ring_edge_and_device_failures(driver, budget, max_batch, nreq, seed, edges):
+    r = subprocess.run([driver, str(budget), str(max_batch), str(nreq), str(seed), str(edges)],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert r.stdout.startswith(f"ok {nreq}")
