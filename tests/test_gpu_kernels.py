@@ -105,3 +105,26 @@ def test_set_kernel_rejects_unknown_values(ctx, pk):
     with pytest.raises(pk.PulscanError) as e:
         ctx.pulscan_ctx_set_kernel(7)
     assert e.value.status == pk.PULSCAN_EINVAL
+
+
+def test_heavily_flagged_tiles_match_the_dense_route(ctx, pk, oracle_lib):
+    # one trial and a 1-sigma threshold put the thresholds just above the
+    # mean, so the pruning bound flags nearly every lane and the tiles switch
+    # to the dense evaluation: the candidates stay those of the dense route
+    # and of the other kernel, byte for byte
+    n, Z, C = (1 << 18) + 333, 200, 1024
+    x = spectrum(oracle_lib, n, Z, C, seed=77)
+    d = to_device(x)
+    say("heavily flagged tiles")
+    low = pk.make_opts(ntrials=1.0)
+    ctx.pulscan_ctx_set_kernel(pk.PULSCAN_KERNEL_TILED)
+    try:
+        a, na = ctx.pulscan_search_ex(d, Z, C, 1.0, opts=low)
+        b, nb = ctx.pulscan_search_ex(d, Z, C, 1.0, opts=pk.make_opts(ntrials=1.0, dense=True))
+    finally:
+        ctx.pulscan_ctx_set_kernel(pk.PULSCAN_KERNEL_AUTO)
+    assert na == nb and na > 10000
+    assert a.tobytes() == b.tobytes()
+    (c, nc), (e, ne) = both(ctx, pk, lambda: ctx.pulscan_search_ex(d, Z, C, 1.0, opts=low))
+    assert nc == ne == na
+    assert c.tobytes() == e.tobytes() == a.tobytes()
