@@ -91,7 +91,9 @@ typedef struct {
   float sigma;        /* Bonferroni-corrected Gaussian-equivalent significance    */
   uint32_t chunk;     /* chunk index, bin / chunk (of the exact bin)              */
   uint32_t harmonics; /* harmonic stage H (1: the power itself), section 2.3      */
-  uint32_t reserved;
+  float logp;         /* natural log of the Bonferroni-corrected p-value of which
+                         sigma is the Gaussian equivalent (the log probability
+                         of section 2.6), at most 0                              */
 } pulscan_candidate;  /* 32 bytes */
 
 /* Caller-owned candidate buffer. */

@@ -41,12 +41,12 @@ class pulscan_candidate(ctypes.Structure):
     _fields_ = [("spectrum", ctypes.c_uint32), ("bin", ctypes.c_uint32),
                 ("width", ctypes.c_uint32), ("power", ctypes.c_float),
                 ("sigma", ctypes.c_float), ("chunk", ctypes.c_uint32),
-                ("harmonics", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("harmonics", ctypes.c_uint32), ("logp", ctypes.c_float)]
 
 
 CANDIDATE_DTYPE = np.dtype([("spectrum", np.uint32), ("bin", np.uint32), ("width", np.uint32),
                             ("power", np.float32), ("sigma", np.float32), ("chunk", np.uint32),
-                            ("harmonics", np.uint32), ("reserved", np.uint32)])
+                            ("harmonics", np.uint32), ("logp", np.float32)])
 
 
 class pulscan_candidates(ctypes.Structure):

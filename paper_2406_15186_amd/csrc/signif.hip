@@ -273,7 +273,8 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
       pw = power32_window(d, p.block, p.from_power, e.bin, w);
       lp = log_sf_chi2_even((double)pw, w * d.dofmul) + log(d.ntrials);
     }
-    const double sg = sigma_from_logp(lp < 0.0 ? lp : 0.0);
+    const double lpc = lp < 0.0 ? lp : 0.0;
+    const double sg = sigma_from_logp(lpc);
     const bool keep = !recheck || sg >= (double)p.sigma;
     pulscan_candidate c;
     c.spectrum = d.spec_id;
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(EmitParams p, SpecDe
     c.sigma = keep ? (float)sg : NAN;
     c.chunk = e.bin / p.chunk;
     c.harmonics = d.harm;
-    c.reserved = 0u;
+    c.logp = (float)lpc;
     if (dest < p.capacity) p.out[dest] = c;
   }
 }

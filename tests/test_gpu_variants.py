@@ -64,16 +64,21 @@ def test_candidate_sigma_at_gpu_power(ctx, pk, oracle_lib, nbins, Z, C, numharm,
     got, cnt = ctx.pulscan_search_ex(to_device(x), Z, C, sig,
                                      opts=pk.make_opts(numharm=numharm))
     assert cnt == len(got) > 0
-    worst = 0.0
+    worst = worst_lp = 0.0
     for c in got:
         H = int(c["harmonics"])
         nt = float((nbins // H) * Z)
-        ref = oracle_lib.candidate_sigma(float(c["power"]), int(c["width"]) * H * (H + 1) // 2, nt)
+        dof = int(c["width"]) * H * (H + 1) // 2
+        ref = oracle_lib.candidate_sigma(float(c["power"]), dof, nt)
         worst = max(worst, abs(float(c["sigma"]) - ref) / max(1.0, abs(ref)))
+        # the log probability of section 2.6 the significance comes from
+        ref_lp = oracle_lib.log_p_corrected(float(c["power"]), dof, nt)
+        worst_lp = max(worst_lp, abs(float(c["logp"]) - ref_lp) / max(1.0, abs(ref_lp)))
     say(f"sigma at GPU power n={nbins} Z={Z} H<={numharm} threshold {sig}: {len(got)} candidates "
         f"(sigma {float(got['sigma'].min()):.2f}..{float(got['sigma'].max()):.2f}), "
-        f"max relative difference {worst:.2e}")
+        f"max relative difference {worst:.2e}, log p {worst_lp:.2e}")
     assert worst <= 2e-6
+    assert worst_lp <= 2e-6
     if sig < 1.0:
         assert float(got["sigma"].min()) < 2.0
 
