@@ -315,7 +315,9 @@ int pulscan_search_noalloc(const pulscan_complex *spectrum, size_t nbins, int zm
 typedef struct pulscan_server pulscan_server;
 
 typedef struct {
-  uint64_t hbm_budget;     /* bytes of spectra in flight (default 4 GiB)              */
+  uint64_t hbm_budget;     /* bytes of spectra in flight (default 4 GiB); 0 = half of
+                              the device memory free when the server starts.  A
+                              budget beyond the free device memory is refused     */
   int32_t max_batch;       /* spectra per launch (default 256)                        */
   int32_t chunk;           /* chunk of every search (default 1024)                    */
   float sigma_thresh;      /* default 6                                               */
@@ -339,9 +341,16 @@ typedef struct {
 /* Defaults as listed in pulscan_server_config. */
 void pulscan_server_config_default(pulscan_server_config *cfg);
 
-/* Create a server on `device`; EINVAL for bad settings, ENOMEM if its device
- * memory cannot be allocated. */
+/* Create a server on `device`; EINVAL for bad settings, ENOMEM if the budget
+ * exceeds the device's free memory or the server's buffers cannot be
+ * allocated.  While it runs, a set is launched only when the device has at
+ * least 256 MiB free for the search's scratch, else once the sets in flight
+ * have finished (admission by free device memory). */
 int pulscan_server_create(pulscan_server **srv, int device, const pulscan_server_config *cfg);
+
+/* The server's budget in bytes (as configured, or taken from the free device
+ * memory for hbm_budget = 0). */
+int pulscan_server_budget(pulscan_server *srv, uint64_t *bytes);
 
 /* Finish every submitted spectrum, stop the worker and free everything. */
 void pulscan_server_destroy(pulscan_server *srv);

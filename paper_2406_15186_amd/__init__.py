@@ -115,6 +115,7 @@ SIGNATURES = {
                                                ctypes.c_int32]),
     "pulscan_server_poll": (_i, [_vp, ctypes.POINTER(pulscan_result), _i, _i]),
     "pulscan_server_stats": (_i, [_vp] + [ctypes.POINTER(ctypes.c_uint64)] * 4),
+    "pulscan_server_budget": (_i, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
     "pulscan_host_alloc": (_i, [ctypes.POINTER(_vp), ctypes.c_uint64]),
     "pulscan_host_free": (None, [_vp]),
 }
@@ -442,6 +443,13 @@ class Server:
                 ctypes.memmove(c.ctypes.data, r.candidates, r.count * CANDIDATE_DTYPE.itemsize)
             out.append((r.ticket, r.status, r.total, r.t_submit, r.t_start, r.t_done, c))
         return out
+
+    def pulscan_server_budget(self) -> int:
+        """The server's budget in bytes (as configured, or half the free
+        device memory at creation for hbm_budget = 0)."""
+        b = ctypes.c_uint64()
+        _check(lib().pulscan_server_budget(self._srv, ctypes.byref(b)), "pulscan_server_budget")
+        return int(b.value)
 
     def pulscan_server_stats(self):
         v = [ctypes.c_uint64() for _ in range(4)]

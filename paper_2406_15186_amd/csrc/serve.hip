@@ -124,6 +124,19 @@ void ring_release_to(pulscan_server *s, uint64_t end) {
   if (s->ring_used == 0) s->ring_head = s->ring_tail = 0;
 }
 
+// Device memory a launch may need for its search's scratch (candidate pool,
+// tile words, outputs) beyond what the server holds.
+constexpr uint64_t kFreeReserve = 256ull << 20;
+
+bool device_has_room() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // no answer: do not hold the queue on it
+  }
+  return (uint64_t)free_b >= kFreeReserve;
+}
+
 // Copy the oldest in-flight set's results out and publish them.
 void collect(pulscan_server *s) {
   const int k = s->order.front();
@@ -199,7 +212,9 @@ void work(pulscan_server *s) {
   for (;;) {
     // admit a set: FIFO, as long as the device budget and the ring allow
     std::vector<Request> set;
-    const bool slot_free = !s->slots[s->next_slot].busy;
+    // a further set only while the device keeps memory free for its search's
+    // scratch, unless nothing is in flight (then it runs and fails alone)
+    const bool slot_free = !s->slots[s->next_slot].busy && (s->order.empty() || device_has_room());
     if (slot_free) {
       while (!s->pending.empty() && (int)set.size() < s->cfg.max_batch) {
         Request &r = s->pending.front();
@@ -271,7 +286,8 @@ void work(pulscan_server *s) {
       continue;
     }
     if (!s->order.empty()) {
-      // nothing more can be admitted now: finish the oldest set
+      // nothing more can be admitted now (or the device is short of free
+      // memory for another set's scratch): finish the oldest set
       lk.unlock();
       collect(s);
       lk.lock();
@@ -300,14 +316,26 @@ void pulscan_server_config_default(pulscan_server_config *c) {
 int pulscan_server_create(pulscan_server **out, int device, const pulscan_server_config *cfg) {
   if (!out || !cfg) return PULSCAN_EINVAL;
   *out = nullptr;
-  if (cfg->hbm_budget < (1ull << 20) || cfg->max_batch < 1 || cfg->chunk < 64 ||
-      cfg->max_candidates < 1 || !(cfg->sigma_thresh == cfg->sigma_thresh))
+  if ((cfg->hbm_budget != 0 && cfg->hbm_budget < (1ull << 20)) || cfg->max_batch < 1 ||
+      cfg->chunk < 64 || cfg->max_candidates < 1 || !(cfg->sigma_thresh == cfg->sigma_thresh))
     return PULSCAN_EINVAL;
   if (cfg->opts.async || cfg->opts.graph || cfg->opts.stream) return PULSCAN_EINVAL;
+  // the budget against the device memory free now
+  size_t free_b = 0, total_b = 0;
+  if (hipSetDevice(device) != hipSuccess || hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return PULSCAN_EHIP;
+  }
+  const uint64_t out_bytes =
+      (uint64_t)kInFlight * ((uint64_t)cfg->max_candidates * sizeof(pulscan_candidate) + 256);
+  uint64_t budget = cfg->hbm_budget;
+  if (budget == 0) budget = ((uint64_t)free_b / 2) & ~255ull;
+  if (budget < (1ull << 20) || budget + out_bytes > (uint64_t)free_b) return PULSCAN_ENOMEM;
   pulscan_server *s = new (std::nothrow) pulscan_server();
   if (!s) return PULSCAN_ENOMEM;
   s->device = device;
   s->cfg = *cfg;
+  s->cfg.hbm_budget = budget;
   int st = pulscan_ctx_create(&s->ctx, device);
   if (st) {
     delete s;
@@ -318,7 +346,7 @@ int pulscan_server_create(pulscan_server **out, int device, const pulscan_server
             hipStreamCreate(&s->compute_stream) == hipSuccess;
   // the ring places copies at 256-byte boundaries: sized to the budget rounded
   // up, so that every spectrum the budget admits also fits in it
-  s->ring_bytes = (cfg->hbm_budget + 255) & ~255ull;
+  s->ring_bytes = (budget + 255) & ~255ull;
   ok = ok && hipMalloc(reinterpret_cast<void **>(&s->ring), s->ring_bytes) == hipSuccess;
   for (int k = 0; ok && k < kInFlight; ++k) {
     Slot &sl = s->slots[k];
@@ -416,6 +444,12 @@ int pulscan_server_poll(pulscan_server *s, pulscan_result *res, int max_results,
     res[i].candidates = d.cands.empty() ? nullptr : d.cands.data();
   }
   return k;
+}
+
+int pulscan_server_budget(pulscan_server *s, uint64_t *bytes) {
+  if (!s || !bytes) return PULSCAN_EINVAL;
+  *bytes = s->cfg.hbm_budget;
+  return PULSCAN_OK;
 }
 
 int pulscan_server_stats(pulscan_server *s, uint64_t *pending, uint64_t *completed,

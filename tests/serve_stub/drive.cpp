@@ -25,6 +25,18 @@ int main(int argc, char **argv) {
   cfg.chunk = 64;
   const int nreq = atoi(argv[3]);
   std::mt19937 rng(atoi(argv[4]));
+  if (nreq == 0) {
+    // creation only: report the status and the budget the server took
+    pulscan_server *srv = nullptr;
+    const int st = pulscan_server_create(&srv, 0, &cfg);
+    uint64_t b = 0;
+    if (st == PULSCAN_OK) {
+      if (pulscan_server_budget(srv, &b) != PULSCAN_OK) return 12;
+      pulscan_server_destroy(srv);
+    }
+    printf("create %d budget %llu\n", st, (unsigned long long)b);
+    return 0;
+  }
   pulscan_server *srv = nullptr;
   if (pulscan_server_create(&srv, 0, &cfg) != PULSCAN_OK) return 3;
   std::vector<std::vector<pulscan_complex>> data(nreq);

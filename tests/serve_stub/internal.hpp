@@ -34,6 +34,14 @@ inline hipError_t hipMalloc(void **p, size_t n) {
   return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 inline hipError_t hipFree(void *p) { free(p); return hipSuccess; }
+// free device memory: PULSCAN_STUB_FREE_MIB MiB (default 16 GiB), half the total
+inline hipError_t hipMemGetInfo(size_t *f, size_t *t) {
+  const char *e = getenv("PULSCAN_STUB_FREE_MIB");
+  const size_t mib = e ? (size_t)strtoull(e, nullptr, 10) : ((size_t)16 << 10);
+  *f = mib << 20;
+  *t = 2 * *f;
+  return hipSuccess;
+}
 inline hipError_t hipHostMalloc(void **p, size_t n, int) { return hipMalloc(p, n); }
 inline hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) {

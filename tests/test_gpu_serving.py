@@ -108,3 +108,29 @@ def test_server_rejects_unsearchable_spectra(pk):
             srv.pulscan_server_submit(d.data_ptr(), 4096, 5000, True)  # zmax beyond 4096
     finally:
         srv.close()
+
+
+def test_budget_from_free_device_memory(pk, oracle_lib):
+    # hbm_budget = 0: half the device memory free at creation; a budget beyond
+    # the free memory is refused; the derived budget serves spectra
+    import torch
+    free0, total = torch.cuda.mem_get_info()
+    with pytest.raises(pk.PulscanError) as e:
+        pk.Server(0, hbm_budget=int(total) + (1 << 30))
+    assert e.value.status == pk.PULSCAN_ENOMEM
+    srv = pk.Server(0, hbm_budget=0, max_batch=8, chunk=1024, sigma_thresh=6.0)
+    try:
+        b = srv.pulscan_server_budget()
+        free1, _ = torch.cuda.mem_get_info()
+        say(f"server budget {b / 2**30:.1f} GiB of {free0 / 2**30:.1f} GiB free")
+        assert b % 256 == 0
+        assert 0.4 * free0 <= b <= 0.5 * free0 + (64 << 20)
+        sp = spectra(oracle_lib, 3, seed=57)
+        ds = [to_device(x) for x, _ in sp]
+        tickets = [srv.pulscan_server_submit(d.data_ptr(), d.shape[0], z, True)
+                   for d, (_, z) in zip(ds, sp)]
+        got = drain(srv, len(tickets))
+        assert sorted(got) == sorted(tickets)
+        assert all(r[1] == pk.PULSCAN_OK for r in got.values())
+    finally:
+        srv.close()

@@ -62,3 +62,29 @@ def test_ring_edge_and_device_failures(driver, budget, max_batch, nreq, seed, ed
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert r.stdout.startswith(f"ok {nreq}")
+
+
+# admission by free device memory: a budget of 0 takes half of what is free
+# (rounded down to the ring's 256-byte placement); a budget beyond what is free
+# (with the server's own candidate buffers) is refused; a device short of
+# room for another set's scratch (under 256 MiB free) serves one set at a time
+@pytest.mark.parametrize("free_mib,budget,status,expect", [
+    (1024, 0, 0, 512 << 20),
+    (1000, 0, 0, 500 << 20),
+    (256, 1 << 30, -2, 0),
+    (100, 64 << 20, -2, 0),       # 64 MiB of spectra + 64 MiB of candidate buffers
+])
+def test_budget_from_free_device_memory(driver, free_mib, budget, status, expect):
+    env = dict(os.environ, PULSCAN_STUB_FREE_MIB=str(free_mib))
+    r = subprocess.run([driver, str(budget), "4", "0", "1"], capture_output=True, text=True,
+                       timeout=60, env=env)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert r.stdout.split() == ["create", str(status), "budget", str(expect)]
+
+
+def test_low_free_memory_serves_one_set_at_a_time(driver):
+    env = dict(os.environ, PULSCAN_STUB_FREE_MIB="200")
+    r = subprocess.run([driver, str(1 << 20), "3", "120", "11"], capture_output=True, text=True,
+                       timeout=60, env=env)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert r.stdout.startswith("ok 120")
