@@ -663,6 +663,10 @@ __device__ __forceinline__ void exact_unit(const Ring<K> &R, uint32_t q, uint32_
   }
   if (pass == 0 && fb == 0 && lane < (uint32_t)K) {
     // windows inside the own group: lane s sums from its start, in order
+    // (zmax passes through an empty asm so that the K tests on it are made
+    // here, not hoisted out of the workgroup's loops into K live masks)
+    uint32_t zm = zmax;
+    asm volatile("" : "+s"(zm));
     float t = 0.f;
 #pragma unroll
     for (int u0 = 0; u0 < K; u0 += 8) {
@@ -675,7 +679,7 @@ __device__ __forceinline__ void exact_unit(const Ring<K> &R, uint32_t q, uint32_
       for (int k = 0; k < 8 && u0 + k < K; ++k) {
         const int u = u0 + k;
         t = u == 0 ? v[0] : t + v[k];
-        if (lane + u < (uint32_t)K && (uint32_t)u < zmax && t >= Tl[u])
+        if (lane + u < (uint32_t)K && (uint32_t)u < zm && t >= Tl[u])
           atomicMax(&slot_row[u], slot_key(t, bin0 + lane));
       }
     }
@@ -923,14 +927,15 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         // width block), one per wave at a time; a lane's passes go to
         // consecutive waves
         float *xs = reinterpret_cast<float *>(lds + p.g.off_xs) + wave * xs_floats<K>();
-        const uint32_t ln = ftid() & 63;
         const uint32_t np = (zmax + 63) / 64;
         for (uint32_t u = wave; u < nitems * np; u += kStreamWaves) {
           const uint32_t it = items[u / np], pass = u % np, fb = it & 0xFFFu;
           if (fb * K + 1 + 64 * pass > zmax) continue;  // past the lane's widths (uniform)
           const uint32_t L = it >> 12;
+          // the lane index taken afresh per unit: its masks and addresses are
+          // rebuilt here rather than held across the workgroup's loops
           exact_unit<K>(R, R.wrap(gb + L), fb, pass, Tl, zmax, nblk,
-                        slots + (size_t)((L * K) / C) * zmax, tb0 + L * K, xs, ln);
+                        slots + (size_t)((L * K) / C) * zmax, tb0 + L * K, xs, ftid() & 63);
         }
       } else {
         // units (lane, width block, start group): lane-major pairs, every 64
