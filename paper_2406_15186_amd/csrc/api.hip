@@ -88,7 +88,7 @@ struct pulscan_ctx {
   std::vector<SpecDesc> last_pdescs;
   // streaming kernel: per-workgroup counts and prefixes, the launch
   // generation and the published halo statistics
-  DevBuf wg_word, wg_prefix, gen, halo;
+  DevBuf wg_word, wg_prefix, gen, halo, seg_ctr;
   int n_cu = 0;
   int kernel = PULSCAN_KERNEL_AUTO;  // which bank kernel serves a search (pulscan_ctx_set_kernel)
   int last_kernel = -1;              // the bank kernel of the last launch
@@ -535,12 +535,16 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
   // the streaming kernel's workgroups: as many as are resident, each range
   // at least a batch and the halo long
   const uint64_t min_range = sgeo.lag > (uint32_t)kStreamBatch ? sgeo.lag : (uint64_t)kStreamBatch;
-  uint64_t nwg = 0;
+  uint64_t nwg = 0, nseg = 0;
   if (sk) {
     nwg = (uint64_t)occ * (uint64_t)ctx->n_cu;
     const uint64_t by_size = blocks / min_range;
     nwg = by_size < nwg ? by_size : nwg;
     if (nwg < 1) nwg = 1;
+    // long launches (a batch): several ranges per workgroup, taken in turn
+    uint64_t rounds = blocks / (nwg * kStreamRangeMin);
+    rounds = rounds > kStreamRounds ? kStreamRounds : rounds;
+    nseg = nwg * (rounds > 1 ? rounds : 1);
   }
   if (search || sk) {
     st = grow(ctx, ctx->counters, sizeof(Counters), true);
@@ -583,13 +587,15 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     }
   }
   if (sk) {
-    st = grow(ctx, ctx->wg_word, nwg * sizeof(unsigned long long), true);
+    st = grow(ctx, ctx->wg_word, nseg * sizeof(unsigned long long), true);
     if (st) return st;
-    st = grow(ctx, ctx->wg_prefix, (nwg + 1) * sizeof(uint32_t), false);
+    st = grow(ctx, ctx->wg_prefix, (nseg + 1) * sizeof(uint32_t), false);
     if (st) return st;
     st = grow(ctx, ctx->gen, sizeof(uint32_t), true);
     if (st) return st;
-    st = grow(ctx, ctx->halo, nwg * sgeo.lag * 4 * sizeof(unsigned long long), true);
+    st = grow(ctx, ctx->halo, nseg * sgeo.lag * 4 * sizeof(unsigned long long), true);
+    if (st) return st;
+    st = grow(ctx, ctx->seg_ctr, 2 * sizeof(uint32_t), true);
     if (st) return st;
   }
 
@@ -626,6 +632,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     sp.total_blocks = blocks;
     sp.align = 1;
     sp.nwg = (uint32_t)nwg;
+    sp.nseg = (uint32_t)nseg;
     sp.chunk = a.chunk;
     sp.block = sblock;
     sp.zmax_max = zmax_max;
@@ -640,6 +647,7 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     sp.wg_word = static_cast<unsigned long long *>(ctx->wg_word.p);
     sp.wg_prefix = static_cast<uint32_t *>(ctx->wg_prefix.p);
     sp.gen = static_cast<uint32_t *>(ctx->gen.p);
+    sp.seg_ctr = static_cast<uint32_t *>(ctx->seg_ctr.p);
     sp.halo = static_cast<unsigned long long *>(ctx->halo.p);
     sp.total = &cnt->total;
     sp.total2 = bp.total2;
@@ -1129,7 +1137,7 @@ void pulscan_ctx_destroy(pulscan_ctx *ctx) {
                     &ctx->allbuf, &ctx->hpow,   &ctx->hsum,     &ctx->hjobs,
                     &ctx->tune_out, &ctx->stats,  &ctx->pdescs,
                     &ctx->span_sum, &ctx->span_prefix, &ctx->wg_word, &ctx->wg_prefix,
-                    &ctx->gen,      &ctx->halo};
+                    &ctx->gen,      &ctx->halo,      &ctx->seg_ctr};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);

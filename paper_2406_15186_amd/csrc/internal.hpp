@@ -141,6 +141,13 @@ hipError_t launch_bank(const Geometry &g, const BankParams &p, uint64_t grid, hi
 constexpr int kStreamWaves = 8;                       // waves per workgroup
 constexpr int kStreamThreads = 64 * kStreamWaves;
 constexpr int kStreamBatch = kStreamWaves;            // blocks normalised per batch
+// A long launch is cut into up to kStreamRounds ranges per workgroup, each
+// of at least kStreamRangeMin blocks; a workgroup that has finished a range
+// takes the next one not yet taken, so that workgroups slowed by their
+// series (zmax, flagged lanes) or by their CU take fewer, and all finish
+// within about one range of each other
+constexpr uint32_t kStreamRounds = 16;
+constexpr uint64_t kStreamRangeMin = 256;
 constexpr uint32_t kStreamSpin = 1u << 20;            // polls of a cross-workgroup word before giving up
 
 struct StreamGeometry {
@@ -161,7 +168,8 @@ struct StreamParams {
   int nspec;
   uint64_t total_blocks;   // padded blocks of the whole launch
   uint32_t align;          // blocks per alignment unit (range boundaries)
-  uint32_t nwg;            // workgroups (= ranges)
+  uint32_t nwg;            // workgroups
+  uint32_t nseg;           // ranges: workgroup w takes ranges w, w + nwg, ... (nseg >= nwg)
   uint32_t chunk;          // C
   uint32_t block;          // normalisation block B (the streaming unit of power input)
   uint32_t zmax_max;
@@ -174,10 +182,11 @@ struct StreamParams {
   StageEntry *pool;
   uint32_t pool_cap;
   uint32_t *pool_head;     // re-armed to 0 by the scan
-  unsigned long long *wg_word;   // per workgroup: (tag << 32) | candidates staged
-  uint32_t *wg_prefix;     // per workgroup exclusive prefix; [nwg] = total
+  unsigned long long *wg_word;   // per range: (tag << 32) | candidates staged
+  uint32_t *wg_prefix;     // per range exclusive prefix; [nseg] = total
   uint32_t *gen;           // launch generation; tags are gen + 1
-  unsigned long long *halo;      // per workgroup: lag x 4 published statistics words
+  uint32_t *seg_ctr;       // two range counters (launch tag parity), or null: ranges in turn
+  unsigned long long *halo;      // per range: lag x 4 published statistics words
   unsigned long long *total;
   unsigned long long *total2;
   uint32_t *overflow;      // 1: pool too small; 2: a count never arrived

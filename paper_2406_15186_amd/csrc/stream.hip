@@ -1,8 +1,14 @@
-// The streaming bank kernel: one persistent workgroup per contiguous range of
-// normalisation blocks does normalisation, power, the boxcar bank of every
-// width, the per-chunk maxima with the threshold test and the staging of the
-// candidates, reading every bin of its range from HBM once.
+// The streaming bank kernel: persistent workgroups, each taking contiguous
+// ranges of normalisation blocks, do normalisation, power, the boxcar bank of
+// every width, the per-chunk maxima with the threshold test and the staging
+// of the candidates, reading every bin of a range from HBM once.
 //
+//  * Ranges.  A launch is cut into nseg equal ranges.  Workgroup w takes
+//    range w, then the next range that no workgroup has taken (a counter in
+//    global memory), so that the workgroups a batch's series slow down (a
+//    larger zmax, a tone's flagged lanes, a busier CU) take fewer ranges and
+//    every workgroup ends within about one range of the others.  Single
+//    spectra use one range per workgroup.
 //  * Streaming.  A workgroup's range (a run of blocks of one or more series)
 //    is taken a batch of kStreamBatch blocks at a time, one block per wave.
 //    The next batch's loads are in flight (in registers) while the current
@@ -16,7 +22,9 @@
 //    statistics of its first `lag` blocks as soon as it has them; the
 //    neighbour then reads only the bins its windows need and normalises them
 //    with those statistics (the same arithmetic, so the same bits).  A word
-//    that does not arrive in time is recomputed from the block itself.
+//    that does not arrive in time is recomputed from the block itself; with
+//    several ranges per workgroup, neighbouring ranges run at unrelated
+//    times and each range normalises its halo blocks itself.
 //  * Normalisation (section 2.2.3; section 2.5 and the appendix algorithm
 //    "Median of Medians Normalisation"): lane l of a wave holds elements
 //    l + 64m of its block, so the first levels of the median-of-4 tree stay
@@ -103,6 +111,13 @@ __device__ __forceinline__ uint32_t sord(float f) {
 }
 __device__ __forceinline__ float sunord(uint32_t o) {
   return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+// A wave-uniform 64-bit value in scalar registers (a division's result is
+// computed in vector registers, where it would hold two of them).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+         __builtin_amdgcn_readfirstlane((uint32_t)v);
 }
 
 // threadIdx.x through an empty asm statement, so that each phase recomputes
@@ -666,7 +681,7 @@ __device__ __forceinline__ void exact_unit(const Ring<K> &R, uint32_t q, uint32_
     // (zmax passes through an empty asm so that the K tests on it are made
     // here, not hoisted out of the workgroup's loops into K live masks)
     uint32_t zm = zmax;
-    asm volatile("" : "+s"(zm));
+    asm volatile("" : "+v"(zm));
     float t = 0.f;
 #pragma unroll
     for (int u0 = 0; u0 < K; u0 += 8) {
@@ -715,6 +730,7 @@ struct Shared {
   uint32_t items[3];  // flagged lanes of a tile (tile t counts in items[t % 3])
   uint32_t lost;
   uint32_t base;
+  uint32_t next;      // the range taken next
   uint32_t wsum[kStreamWaves];
 };
 
@@ -776,13 +792,12 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
   const uint32_t wg = blockIdx.x;
   const uint32_t tag = *gp(p.gen) + 1u;
   const uint64_t units = p.total_blocks / p.align;
-  const uint64_t g0 = units * wg / nwg * p.align, g1 = units * (wg + 1) / nwg * p.align;
+  const uint32_t nseg = p.nseg;
   const bool search = PRUNE || p.mode == kModeSearch;
   constexpr bool prune = PRUNE;
   NormOut no{};
   no.P_out = !PRUNE && p.mode == kModeTables ? p.P_out : nullptr;
   no.stats_out = !PRUNE && p.mode == kModeTables ? p.stats_out : nullptr;
-  uint32_t wg_count = 0;  // candidates staged so far by this workgroup (uniform)
   uint32_t tc = 0;        // tiles banked so far (uniform)
   if (threadIdx.x == 0) {
     sh.items[0] = 0u;
@@ -790,360 +805,384 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     sh.items[2] = 0u;
   }
 
-  // the series holding block g0
-  int s = 0;
-  if (nspec > 1) {
-    int lo = 0, hi = nspec - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (((const CAS SpecDesc *)descs)[mid].block_begin <= g0)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    s = lo;
-  }
-  uint64_t gc = g0;
-  while (gc < g1 && s < nspec) {
-    const Series d = nspec == 1 ? Series{p.single.x, p.single.thr, p.single.block_begin,
-                                         p.single.n, p.single.zmax, p.single.zc}
-                                : series_at(descs, s);
-    const uint32_t nbs = (d.n + B - 1) / B;
-    if (gc < d.block_begin) gc = d.block_begin;
-    if (gc >= g1) break;
-    if (gc >= d.block_begin + nbs) {  // padding after the series
-      ++s;
-      continue;
-    }
-    const uint32_t a = (uint32_t)(gc - d.block_begin);
-    const uint32_t b = (uint32_t)min(g1 - d.block_begin, (uint64_t)nbs);
-    const uint32_t n = d.n, zmax = d.zmax, zc = d.zc, nblk = zc / K;
-    const uint32_t lgs = (zc + B - 1) / B;       // halo blocks of this series
-    const bool publish = a > 0 && gc == g0;      // the previous range needs our first blocks
-    const bool consume = b < nbs;                // our last tile reaches into the next range
-    const uint32_t zpub = min(lgs, b - a);
+  // the ranges of this workgroup, of nseg equal ones: range w first, then
+  // the next one not yet taken (from the launch's counter) or, without a
+  // counter, w + nwg, w + 2 nwg, ...  The counters alternate between
+  // launches: launch tag t takes from seg_ctr[t & 1], whose last increments
+  // may come after the scan, and the scan re-arms seg_ctr[(t + 1) & 1] for
+  // the next launch.
+  uint32_t *const seg_ctr = p.seg_ctr ? p.seg_ctr + (tag & 1u) : nullptr;
+  for (uint32_t seg = wg; seg < nseg;) {
+    // (the divisor through an empty asm: the division's set-up is then made
+    // here, once per range, instead of held in registers across the loop)
+    uint32_t ns = nseg;
+    asm volatile("" : "+s"(ns));
+    const uint64_t g0 = uniform64(units * seg / ns * p.align);
+    const uint64_t g1 = uniform64(units * (seg + 1) / ns * p.align);
+    uint32_t wg_count = 0;  // candidates staged so far in this range (uniform)
 
-    // this series' first thresholds, then the first batch's loads (loads
-    // complete in order, so the thresholds can be stored before the spectrum
-    // arrives), then the set-up
-    const float thr0 = threadIdx.x < zc ? gp(d.thr)[threadIdx.x] : 0.f;
-    const uint32_t nbat = (b - a + NB - 1) / NB;
-    Raw<EPL, FP> cur, nxt;
-    // issue the loads of batch j into r: block a + jNB + wave, or, for
-    // j == nbat, the halo block b + wave's first bins
-    // Every wave issues the same number of loads on every path (a wave with
-    // no block re-reads the range's last one, never used), so that waiting
-    // for one set never waits for the next.
-    auto issue = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
-      if (j < nbat) {
-        load_block<EPL, FP>(d, min(a + j * NB + wave, b - 1), r);
-      } else {
-        const bool halo = j == nbat && consume && wave < lgs && b + wave < nbs;
-        const uint32_t need = halo ? min(B, (zc - wave * B + 63) / 64 * 64) : B;
-        load_prefix<EPL, FP>(d, halo ? b + wave : b - 1, need, r);
+    // the series holding block g0
+    int s = 0;
+    if (nspec > 1) {
+      int lo = 0, hi = nspec - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (((const CAS SpecDesc *)descs)[mid].block_begin <= g0)
+          lo = mid;
+        else
+          hi = mid - 1;
       }
-    };
-    issue(0, cur);
-
-    // thresholds of the series, and the bound's minima of them
-    __syncthreads();
-    if (threadIdx.x < zc) Tl[threadIdx.x] = thr0;
-    if (zc > nthr) {  // zmax above 512 (uniform)
-      for (uint32_t i = ftid() + nthr; i < zc; i += nthr) Tl[i] = gp(d.thr)[i];
+      s = lo;
     }
-    __syncthreads();
-    {
-      // the first block's sub-ranges, widths 1..4, 5..8, 9..16 (those that
-      // exist), and every width block
-      const uint32_t tid = ftid();
-      if (tid == 0) {
-        float m0 = Tl[0], m1 = INFINITY, m2 = INFINITY;
-#pragma unroll
-        for (int w = 1; w < K; ++w) {
-          if (w < 4) m0 = fminf(m0, Tl[w]);
-          else if (w < 8) m1 = fminf(m1, Tl[w]);
-          else m2 = fminf(m2, Tl[w]);
+    uint64_t gc = g0;
+    while (gc < g1 && s < nspec) {
+      const Series d = nspec == 1 ? Series{p.single.x, p.single.thr, p.single.block_begin,
+                                           p.single.n, p.single.zmax, p.single.zc}
+                                  : series_at(descs, s);
+      const uint32_t nbs = (d.n + B - 1) / B;
+      if (gc < d.block_begin) gc = d.block_begin;
+      if (gc >= g1) break;
+      if (gc >= d.block_begin + nbs) {  // padding after the series
+        ++s;
+        continue;
+      }
+      const uint32_t a = (uint32_t)(gc - d.block_begin);
+      const uint32_t b = (uint32_t)min(g1 - d.block_begin, (uint64_t)nbs);
+      const uint32_t n = d.n, zmax = d.zmax, zc = d.zc, nblk = zc / K;
+      const uint32_t lgs = (zc + B - 1) / B;       // halo blocks of this series
+      // the previous range needs our first blocks; with several ranges per
+      // workgroup the ranges' neighbours run at unrelated times, and each
+      // range normalises its halo blocks itself (lag blocks in a range of at
+      // least kStreamRangeMin)
+      const bool publish = nseg == nwg && a > 0 && gc == g0;
+      const bool consume = b < nbs;                // our last tile reaches into the next range
+      const uint32_t zpub = min(lgs, b - a);
+
+      // this series' first thresholds, then the first batch's loads (loads
+      // complete in order, so the thresholds can be stored before the spectrum
+      // arrives), then the set-up
+      const float thr0 = threadIdx.x < zc ? gp(d.thr)[threadIdx.x] : 0.f;
+      const uint32_t nbat = (b - a + NB - 1) / NB;
+      Raw<EPL, FP> cur, nxt;
+      // issue the loads of batch j into r: block a + jNB + wave, or, for
+      // j == nbat, the halo block b + wave's first bins
+      // Every wave issues the same number of loads on every path (a wave with
+      // no block re-reads the range's last one, never used), so that waiting
+      // for one set never waits for the next.
+      auto issue = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
+        if (j < nbat) {
+          load_block<EPL, FP>(d, min(a + j * NB + wave, b - 1), r);
+        } else {
+          const bool halo = j == nbat && consume && wave < lgs && b + wave < nbs;
+          const uint32_t need = halo ? min(B, (zc - wave * B + 63) / 64 * 64) : B;
+          load_prefix<EPL, FP>(d, halo ? b + wave : b - 1, need, r);
         }
-        Tb1[0] = m0 * kSBoundSlack;
-        Tb1[1] = m1 * kSBoundSlack;
-        Tb1[2] = m2 * kSBoundSlack;
-      }
-      for (uint32_t i = tid; i < nblk; i += nthr) {
-        float m = Tl[i * K];
-#pragma unroll
-        for (int u = 1; u < K; ++u) m = fminf(m, Tl[i * K + u]);
-        Tb[i] = m * kSBoundSlack;
-      }
-    }
+      };
+      issue(0, cur);
 
-    // the halo's statistics words, published by the next range's workgroup
-    const unsigned long long *hw = halo + (size_t)(wg + 1) * lag * 4;
-    unsigned long long *pw = halo + (size_t)wg * lag * 4;
-
-    uint32_t banked = a;
-    no.tag = tag;
-
-    // bank the tile of blocks [t0, t1)
-    auto bank_tile = [&](uint32_t t0, uint32_t t1) __attribute__((always_inline)) {
-      const uint32_t tb0 = t0 * B;
-      const uint32_t tbins = min((t1 - t0) * B, n - tb0);   // window starts
-      const uint32_t nlane = (tbins + K - 1) / K;            // lanes with starts
-      const uint32_t gb = ((t0 - a) % RB) * GPB;             // ring position of the tile's group 0
-      const uint32_t nch = (tbins + C - 1) / C, chunk0 = tb0 / C;
-      const uint32_t nsl = nch * zmax;
-      const uint32_t nbw = (zmax + K - 1) / K;               // width blocks
-      // tile tc counts its flagged lanes in items[tc % 3].  After its first
-      // barrier every thread has read tile tc-1's count, and no thread can
-      // reach tile tc+2's counting before passing tile tc+1's first barrier,
-      // which thread 0 reaches only after clearing items[(tc+2) % 3] here
-      const uint32_t ci = tc % 3;
-      uint32_t *cnt = &sh.items[ci];
-      ++tc;
-      if (prune) {
-        const uint32_t tid = ftid(), ln = tid & 63, wv = tid >> 6;
-        for (uint32_t sg = wv; sg * 64 < nlane; sg += kStreamWaves) {
-          const uint32_t L = sg * 64 + ln;
-          const uint32_t fl = L < nlane ? sbound<K>(R, R.wrap(gb + L), Tb1, Tb, nblk) : nblk;
-          const unsigned long long mask = __ballot(fl < nblk);
-          if (mask) {
-            uint32_t base = 0;
-            if (ln == 0) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
-            base = __shfl(base, 0, 64);
-            if (fl < nblk) items[base + __popcll(mask & ((1ull << ln) - 1ull))] = (L << 12) | fl;
-          }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) sh.items[ci == 0 ? 2 : ci - 1] = 0u;
+      // thresholds of the series, and the bound's minima of them
+      __syncthreads();
+      if (threadIdx.x < zc) Tl[threadIdx.x] = thr0;
+      if (zc > nthr) {  // zmax above 512 (uniform)
+        for (uint32_t i = ftid() + nthr; i < zc; i += nthr) Tl[i] = gp(d.thr)[i];
       }
-      const uint32_t nitems = prune ? *cnt : nlane;
-      if (nitems == 0) return;  // nothing evaluated: no candidate (uniform)
+      __syncthreads();
       {
+        // the first block's sub-ranges, widths 1..4, 5..8, 9..16 (those that
+        // exist), and every width block
         const uint32_t tid = ftid();
-        for (uint32_t i = tid; i < nsl; i += nthr) slots[i] = 0ull;
-        __syncthreads();
-      }
-      if constexpr (PRUNE) {
-        // units (flagged lane, pass of 64 widths from its first flagged
-        // width block), one per wave at a time; a lane's passes go to
-        // consecutive waves
-        float *xs = reinterpret_cast<float *>(lds + p.g.off_xs) + wave * xs_floats<K>();
-        const uint32_t np = (zmax + 63) / 64;
-        for (uint32_t u = wave; u < nitems * np; u += kStreamWaves) {
-          const uint32_t it = items[u / np], pass = u % np, fb = it & 0xFFFu;
-          if (fb * K + 1 + 64 * pass > zmax) continue;  // past the lane's widths (uniform)
-          const uint32_t L = it >> 12;
-          // the lane index taken afresh per unit: its masks and addresses are
-          // rebuilt here rather than held across the workgroup's loops
-          exact_unit<K>(R, R.wrap(gb + L), fb, pass, Tl, zmax, nblk,
-                        slots + (size_t)((L * K) / C) * zmax, tb0 + L * K, xs, ftid() & 63);
+        if (tid == 0) {
+          float m0 = Tl[0], m1 = INFINITY, m2 = INFINITY;
+  #pragma unroll
+          for (int w = 1; w < K; ++w) {
+            if (w < 4) m0 = fminf(m0, Tl[w]);
+            else if (w < 8) m1 = fminf(m1, Tl[w]);
+            else m2 = fminf(m2, Tl[w]);
+          }
+          Tb1[0] = m0 * kSBoundSlack;
+          Tb1[1] = m1 * kSBoundSlack;
+          Tb1[2] = m2 * kSBoundSlack;
         }
-      } else {
-        // units (lane, width block, start group): lane-major pairs, every 64
-        // pairs taken once per start group by whole waves
-        const uint32_t tid = ftid();
-        constexpr uint32_t NH = K / sks<K>();
-        const uint32_t npairs = nitems * nbw;
-        const uint32_t nrun = (npairs + 63) / 64 * 64 * NH;
-        for (uint32_t r0 = 0; r0 < nrun; r0 += nthr) {
-          const uint32_t j = r0 + tid;
-          const uint32_t grp = j >> 6, half = grp % NH;
-          const uint32_t u = (grp / NH) * 64 + (j & 63);
-          const bool ok = j < nrun && u < npairs;
-          const uint32_t it = ok ? (prune ? items[u / nbw] : ((u / nbw) << 12)) : 0u;
-          const uint32_t bw = ok ? u % nbw : 0u;
-          if (ok && bw >= (it & 0xFFFu)) {
-            const uint32_t L = it >> 12;
-            const uint32_t q = R.wrap(gb + L);
-            unsigned long long *row = slots + (size_t)((L * K) / C) * zmax;
-            if constexpr (NH == 1) {
-              eval_unit<K, 0>(R, q, bw, Tl, zmax, row, tb0 + L * K);
-            } else {
-              static_assert(NH == 4, "four start groups of four");
-              if (half == 0)
-                eval_unit<K, 0>(R, q, bw, Tl, zmax, row, tb0 + L * K);
-              else if (half == 1)
-                eval_unit<K, 4>(R, q, bw, Tl, zmax, row, tb0 + L * K);
-              else if (half == 2)
-                eval_unit<K, 8>(R, q, bw, Tl, zmax, row, tb0 + L * K);
-              else
-                eval_unit<K, 12>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+        for (uint32_t i = tid; i < nblk; i += nthr) {
+          float m = Tl[i * K];
+  #pragma unroll
+          for (int u = 1; u < K; ++u) m = fminf(m, Tl[i * K + u]);
+          Tb[i] = m * kSBoundSlack;
+        }
+      }
+
+      // the halo's statistics words, published by the next range's workgroup
+      const unsigned long long *hw = halo + (size_t)(seg + 1) * lag * 4;
+      unsigned long long *pw = halo + (size_t)seg * lag * 4;
+
+      uint32_t banked = a;
+      no.tag = tag;
+
+      // bank the tile of blocks [t0, t1)
+      auto bank_tile = [&](uint32_t t0, uint32_t t1) __attribute__((always_inline)) {
+        const uint32_t tb0 = t0 * B;
+        const uint32_t tbins = min((t1 - t0) * B, n - tb0);   // window starts
+        const uint32_t nlane = (tbins + K - 1) / K;            // lanes with starts
+        const uint32_t gb = ((t0 - a) % RB) * GPB;             // ring position of the tile's group 0
+        const uint32_t nch = (tbins + C - 1) / C, chunk0 = tb0 / C;
+        const uint32_t nsl = nch * zmax;
+        const uint32_t nbw = (zmax + K - 1) / K;               // width blocks
+        // tile tc counts its flagged lanes in items[tc % 3].  After its first
+        // barrier every thread has read tile tc-1's count, and no thread can
+        // reach tile tc+2's counting before passing tile tc+1's first barrier,
+        // which thread 0 reaches only after clearing items[(tc+2) % 3] here
+        const uint32_t ci = tc % 3;
+        uint32_t *cnt = &sh.items[ci];
+        ++tc;
+        if (prune) {
+          const uint32_t tid = ftid(), ln = tid & 63, wv = tid >> 6;
+          for (uint32_t sg = wv; sg * 64 < nlane; sg += kStreamWaves) {
+            const uint32_t L = sg * 64 + ln;
+            const uint32_t fl = L < nlane ? sbound<K>(R, R.wrap(gb + L), Tb1, Tb, nblk) : nblk;
+            const unsigned long long mask = __ballot(fl < nblk);
+            if (mask) {
+              uint32_t base = 0;
+              if (ln == 0) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+              base = __shfl(base, 0, 64);
+              if (fl < nblk) items[base + __popcll(mask & ((1ull << ln) - 1ull))] = (L << 12) | fl;
             }
           }
+          __syncthreads();
+          if (threadIdx.x == 0) sh.items[ci == 0 ? 2 : ci - 1] = 0u;
         }
-      }
-      __syncthreads();
-      const uint32_t tid = ftid(), ln = tid & 63, wv = tid >> 6;
-      if (search) {
-        // stage the tile's maxima in slot order, i.e. (chunk, width) order
-        const uint32_t per = (nsl + nthr - 1) / nthr;
-        const uint32_t lo = min(tid * per, nsl), hi = min(lo + per, nsl);
-        uint32_t mine = 0;
-        for (uint32_t i = lo; i < hi; ++i) mine += slots[i] != 0ull ? 1u : 0u;
-        uint32_t incl = mine;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t v = __shfl_up(incl, o, 64);
-          if (ln >= (uint32_t)o) incl += v;
+        const uint32_t nitems = prune ? *cnt : nlane;
+        if (nitems == 0) return;  // nothing evaluated: no candidate (uniform)
+        {
+          const uint32_t tid = ftid();
+          for (uint32_t i = tid; i < nsl; i += nthr) slots[i] = 0ull;
+          __syncthreads();
         }
-        if (ln == 63) sh.wsum[wv] = incl;
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
-        for (uint32_t v = 0; v < (uint32_t)kStreamWaves; ++v) {
-          before += v < wv ? sh.wsum[v] : 0u;
-          tot += sh.wsum[v];
-        }
-        if (tid == 0) sh.base = tot ? atomicAdd(pool_head, tot) : 0u;
-        __syncthreads();
-        const uint32_t base = sh.base;
-        uint32_t rank = before + incl - mine;
-        for (uint32_t i = lo; i < hi; ++i) {
-          const unsigned long long key = slots[i];
-          if (key == 0ull) continue;
-          const uint32_t pos = base + rank;
-          if (pos < pool_cap) {
-            const uint32_t cl = i / zmax, w = i - cl * zmax + 1;
-            StageEntry e;
-            e.unit = wg;
-            e.rank = wg_count + rank;
-            e.spec = (uint32_t)s;
-            e.bin = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
-            e.power = sunord((uint32_t)(key >> 32));
-            e.width = w;
-            pool[pos] = e;
+        if constexpr (PRUNE) {
+          // units (flagged lane, pass of 64 widths from its first flagged
+          // width block), one per wave at a time; a lane's passes go to
+          // consecutive waves
+          float *xs = reinterpret_cast<float *>(lds + p.g.off_xs) + wave * xs_floats<K>();
+          const uint32_t np = (zmax + 63) / 64;
+          for (uint32_t u = wave; u < nitems * np; u += kStreamWaves) {
+            const uint32_t it = items[u / np], pass = u % np, fb = it & 0xFFFu;
+            if (fb * K + 1 + 64 * pass > zmax) continue;  // past the lane's widths (uniform)
+            const uint32_t L = it >> 12;
+            // the lane index taken afresh per unit: its masks and addresses are
+            // rebuilt here rather than held across the workgroup's loops
+            exact_unit<K>(R, R.wrap(gb + L), fb, pass, Tl, zmax, nblk,
+                          slots + (size_t)((L * K) / C) * zmax, tb0 + L * K, xs, ftid() & 63);
           }
-          ++rank;
-        }
-        wg_count += tot;
-      } else {
-        for (uint32_t i = tid; i < nsl; i += nthr) {
-          const unsigned long long key = slots[i];
-          const size_t o = (size_t)chunk0 * zmax + i;
-          p.M[o] = key ? sunord((uint32_t)(key >> 32)) : -INFINITY;
-          p.I[o] = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : 0xFFFFFFFFu;
-        }
-      }
-      __syncthreads();
-    };
-
-    // Step j normalises batch j (wave w: block a + jNB + w) and banks every
-    // tile whose windows the ring then holds: up to f + NB - lgs, the
-    // batch's end less the halo (the next batch overwrites the blocks before
-    // f + NB - lag), and for the last batch up to b - lgs, so that the
-    // halo's slots are free.  The halo step then normalises the first bins of
-    // blocks b .. b+lgs-1 (wave w: block b + w) and banks up to b.  The next
-    // batches' loads (or the halo's) are in flight while this one is
-    // searched: the two register sets alternate.  Only the first two batches
-    // are not requested together (issued together, they would arrive
-    // interleaved, every workgroup's whole first pair at once, with nothing
-    // to search in the meantime).
-    auto step = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
-      const uint32_t f = a + j * NB;
-      const uint32_t k = f + wave;
-      if (k < b) {
-        NormOut o = no;
-        o.pub = (publish && k - a < zpub) ? pw + 4 * (k - a) : nullptr;
-        normalise<K, EPL, FP>(d, k, r, false, BlockStats{}, B, R, (k - a) % RB, o, lane);
-      }
-      __syncthreads();
-      const uint32_t ready = j + 1 == nbat ? (b > lgs ? b - lgs : 0u)
-                                           : (f + NB > lgs ? f + NB - lgs : 0u);
-      while (banked < ready) {
-        const uint32_t t1 = min(banked + NB, ready);
-        bank_tile(banked, t1);
-        banked = t1;
-      }
-    };
-    // batch 1 is requested once batch 0 has arrived (every load issued so
-    // far); from then on batch j + 2 is requested as soon as batch j has been
-    // normalised, so that two batches are in flight while batch j + 1 is
-    // awaited
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    issue(1, nxt);
-    uint32_t j = 0;
-    while (true) {
-      step(j, cur);
-      if (j + 1 == nbat) break;  // the halo is in nxt
-      issue(j + 2, cur);
-      step(j + 1, nxt);
-      if (j + 2 == nbat) {  // the halo is in cur
-        nxt = cur;
-        break;
-      }
-      issue(j + 3, nxt);
-      j += 2;
-    }
-    {
-      // the halo step
-      const uint32_t k = b + wave;
-      if (wave < lgs) {
-        const uint32_t limit = min(B, (zc - wave * B + 63) / 64 * 64);
-        const uint32_t slot = (k - a) % RB;
-        if (k >= nbs) {
-          // no spectrum behind these bins
-          fill_past_end<K, EPL>(R, slot, limit, lane);
         } else {
-          BlockStats given{};
-          bool use_given = false;
-          if constexpr (!FP) {
-            // the next range's published statistics, or our own
-            unsigned long long v = 0;
-            bool ok = false;
-            // (the word's address from a fresh lane id, so that it is not
-            // computed at the kernel's start and kept live)
-            const uint32_t ln = ftid() & 63;
-            if (ln < 4) {
-              const unsigned long long *hwl = hw + 4 * wave + ln;
-              for (uint32_t it = 0; it < spin; ++it) {
-                v = __hip_atomic_load(hwl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((uint32_t)(v >> 32) == tag) {
-                  ok = true;
-                  break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+          // units (lane, width block, start group): lane-major pairs, every 64
+          // pairs taken once per start group by whole waves
+          const uint32_t tid = ftid();
+          constexpr uint32_t NH = K / sks<K>();
+          const uint32_t npairs = nitems * nbw;
+          const uint32_t nrun = (npairs + 63) / 64 * 64 * NH;
+          for (uint32_t r0 = 0; r0 < nrun; r0 += nthr) {
+            const uint32_t j = r0 + tid;
+            const uint32_t grp = j >> 6, half = grp % NH;
+            const uint32_t u = (grp / NH) * 64 + (j & 63);
+            const bool ok = j < nrun && u < npairs;
+            const uint32_t it = ok ? (prune ? items[u / nbw] : ((u / nbw) << 12)) : 0u;
+            const uint32_t bw = ok ? u % nbw : 0u;
+            if (ok && bw >= (it & 0xFFFu)) {
+              const uint32_t L = it >> 12;
+              const uint32_t q = R.wrap(gb + L);
+              unsigned long long *row = slots + (size_t)((L * K) / C) * zmax;
+              if constexpr (NH == 1) {
+                eval_unit<K, 0>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+              } else {
+                static_assert(NH == 4, "four start groups of four");
+                if (half == 0)
+                  eval_unit<K, 0>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+                else if (half == 1)
+                  eval_unit<K, 4>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+                else if (half == 2)
+                  eval_unit<K, 8>(R, q, bw, Tl, zmax, row, tb0 + L * K);
+                else
+                  eval_unit<K, 12>(R, q, bw, Tl, zmax, row, tb0 + L * K);
               }
             }
-            use_given = __ballot(ok) == 0xFull;
-            if (use_given) {
-              given.med_re = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 0));
-              given.mad_re = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 1));
-              given.med_im = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 2));
-              given.mad_im = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 3));
-            } else {
-              load_block<EPL, FP>(d, k, nxt);
-            }
           }
-          normalise<K, EPL, FP>(d, k, nxt, use_given, given, limit, R, slot, NormOut{}, lane);
+        }
+        __syncthreads();
+        const uint32_t tid = ftid(), ln = tid & 63, wv = tid >> 6;
+        if (search) {
+          // stage the tile's maxima in slot order, i.e. (chunk, width) order
+          const uint32_t per = (nsl + nthr - 1) / nthr;
+          const uint32_t lo = min(tid * per, nsl), hi = min(lo + per, nsl);
+          uint32_t mine = 0;
+          for (uint32_t i = lo; i < hi; ++i) mine += slots[i] != 0ull ? 1u : 0u;
+          uint32_t incl = mine;
+  #pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, 64);
+            if (ln >= (uint32_t)o) incl += v;
+          }
+          if (ln == 63) sh.wsum[wv] = incl;
+          __syncthreads();
+          uint32_t before = 0, tot = 0;
+          for (uint32_t v = 0; v < (uint32_t)kStreamWaves; ++v) {
+            before += v < wv ? sh.wsum[v] : 0u;
+            tot += sh.wsum[v];
+          }
+          if (tid == 0) sh.base = tot ? atomicAdd(pool_head, tot) : 0u;
+          __syncthreads();
+          const uint32_t base = sh.base;
+          uint32_t rank = before + incl - mine;
+          for (uint32_t i = lo; i < hi; ++i) {
+            const unsigned long long key = slots[i];
+            if (key == 0ull) continue;
+            const uint32_t pos = base + rank;
+            if (pos < pool_cap) {
+              const uint32_t cl = i / zmax, w = i - cl * zmax + 1;
+              StageEntry e;
+              e.unit = seg;
+              e.rank = wg_count + rank;
+              e.spec = (uint32_t)s;
+              e.bin = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+              e.power = sunord((uint32_t)(key >> 32));
+              e.width = w;
+              pool[pos] = e;
+            }
+            ++rank;
+          }
+          wg_count += tot;
+        } else {
+          for (uint32_t i = tid; i < nsl; i += nthr) {
+            const unsigned long long key = slots[i];
+            const size_t o = (size_t)chunk0 * zmax + i;
+            p.M[o] = key ? sunord((uint32_t)(key >> 32)) : -INFINITY;
+            p.I[o] = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : 0xFFFFFFFFu;
+          }
+        }
+        __syncthreads();
+      };
+
+      // Step j normalises batch j (wave w: block a + jNB + w) and banks every
+      // tile whose windows the ring then holds: up to f + NB - lgs, the
+      // batch's end less the halo (the next batch overwrites the blocks before
+      // f + NB - lag), and for the last batch up to b - lgs, so that the
+      // halo's slots are free.  The halo step then normalises the first bins of
+      // blocks b .. b+lgs-1 (wave w: block b + w) and banks up to b.  The next
+      // batches' loads (or the halo's) are in flight while this one is
+      // searched: the two register sets alternate.  Only the first two batches
+      // are not requested together (issued together, they would arrive
+      // interleaved, every workgroup's whole first pair at once, with nothing
+      // to search in the meantime).
+      auto step = [&](uint32_t j, Raw<EPL, FP> &r) __attribute__((always_inline)) {
+        const uint32_t f = a + j * NB;
+        const uint32_t k = f + wave;
+        if (k < b) {
+          NormOut o = no;
+          o.pub = (publish && k - a < zpub) ? pw + 4 * (k - a) : nullptr;
+          normalise<K, EPL, FP>(d, k, r, false, BlockStats{}, B, R, (k - a) % RB, o, lane);
+        }
+        __syncthreads();
+        const uint32_t ready = j + 1 == nbat ? (b > lgs ? b - lgs : 0u)
+                                             : (f + NB > lgs ? f + NB - lgs : 0u);
+        while (banked < ready) {
+          const uint32_t t1 = min(banked + NB, ready);
+          bank_tile(banked, t1);
+          banked = t1;
+        }
+      };
+      // batch 1 is requested once batch 0 has arrived (every load issued so
+      // far); from then on batch j + 2 is requested as soon as batch j has been
+      // normalised, so that two batches are in flight while batch j + 1 is
+      // awaited
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      issue(1, nxt);
+      uint32_t j = 0;
+      while (true) {
+        step(j, cur);
+        if (j + 1 == nbat) break;  // the halo is in nxt
+        issue(j + 2, cur);
+        step(j + 1, nxt);
+        if (j + 2 == nbat) {  // the halo is in cur
+          nxt = cur;
+          break;
+        }
+        issue(j + 3, nxt);
+        j += 2;
+      }
+      {
+        // the halo step
+        const uint32_t k = b + wave;
+        if (wave < lgs) {
+          const uint32_t limit = min(B, (zc - wave * B + 63) / 64 * 64);
+          const uint32_t slot = (k - a) % RB;
+          if (k >= nbs) {
+            // no spectrum behind these bins
+            fill_past_end<K, EPL>(R, slot, limit, lane);
+          } else {
+            BlockStats given{};
+            bool use_given = false;
+            if constexpr (!FP) {
+              // the next range's published statistics, or our own
+              unsigned long long v = 0;
+              bool ok = false;
+              // (the word's address from a fresh lane id, so that it is not
+              // computed at the kernel's start and kept live)
+              const uint32_t ln = ftid() & 63;
+              if (ln < 4) {
+                const unsigned long long *hwl = hw + 4 * wave + ln;
+                for (uint32_t it = 0; it < (nseg == nwg ? spin : 0u); ++it) {
+                  v = __hip_atomic_load(hwl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  if ((uint32_t)(v >> 32) == tag) {
+                    ok = true;
+                    break;
+                  }
+                  __builtin_amdgcn_s_sleep(2);
+                }
+              }
+              use_given = __ballot(ok) == 0xFull;
+              if (use_given) {
+                given.med_re = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 0));
+                given.mad_re = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 1));
+                given.med_im = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 2));
+                given.mad_im = __uint_as_float(__builtin_amdgcn_readlane((uint32_t)v, 3));
+              } else {
+                load_block<EPL, FP>(d, k, nxt);
+              }
+            }
+            normalise<K, EPL, FP>(d, k, nxt, use_given, given, limit, R, slot, NormOut{}, lane);
+          }
+        }
+        __syncthreads();
+        while (banked < b) {
+          const uint32_t t1 = min(banked + NB, b);
+          bank_tile(banked, t1);
+          banked = t1;
         }
       }
-      __syncthreads();
-      while (banked < b) {
-        const uint32_t t1 = min(banked + NB, b);
-        bank_tile(banked, t1);
-        banked = t1;
-      }
+      gc = d.block_begin + b;
+      if (b == nbs) ++s;
+      // every load of this series has been consumed: say so, so that the next
+      // series' loads are not held back for ones that might be in flight
+      __builtin_amdgcn_s_waitcnt(0);
     }
-    gc = d.block_begin + b;
-    if (b == nbs) ++s;
-    // every load of this series has been consumed: say so, so that the next
-    // series' loads are not held back for ones that might be in flight
-    __builtin_amdgcn_s_waitcnt(0);
-  }
 
-  // publish this range's count; the last workgroup scans every range's
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // the pool reservations are complete before the count is published, so
-    // the scan (which waits for every count) may re-arm the pool head
-    __builtin_amdgcn_s_waitcnt(0);
-    __hip_atomic_store(p.wg_word + wg, ((unsigned long long)tag << 32) | wg_count,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    sh.lost = 0u;
+    // publish this range's count; the last workgroup scans every range's
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // the pool reservations are complete before the count is published, so
+      // the scan (which waits for every count) may re-arm the pool head
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(p.wg_word + seg, ((unsigned long long)tag << 32) | wg_count,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sh.next = seg_ctr ? nwg + atomicAdd(seg_ctr, 1u) : seg + nwg;
+    }
+    __syncthreads();
+    seg = __builtin_amdgcn_readfirstlane(sh.next);
   }
+  if (threadIdx.x == 0) sh.lost = 0u;
   if (wg != p.nwg - 1) return;
   __syncthreads();
   const uint32_t tid = threadIdx.x;
-  const uint32_t per = (p.nwg + nthr - 1) / nthr;
-  const uint32_t lo = min(tid * per, p.nwg), hi = min(lo + per, p.nwg);
+  const uint32_t per = (nseg + nthr - 1) / nthr;
+  const uint32_t lo = min(tid * per, nseg), hi = min(lo + per, nseg);
   uint32_t mine = 0;
   bool lost = false;
   for (uint32_t i = lo; i < hi; ++i) {
@@ -1181,7 +1220,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
   }
   __syncthreads();
   if (tid == 0) {
-    p.wg_prefix[p.nwg] = tot;
+    p.wg_prefix[nseg] = tot;
     if (search) {
       const uint32_t ovf = sh.lost ? 2u : (tot > p.pool_cap ? 1u : 0u);
       *p.total = tot;
@@ -1191,6 +1230,9 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
       *p.overflow = sh.lost ? 2u : 0u;
     }
     __hip_atomic_store(p.pool_head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p.seg_ctr)
+      __hip_atomic_store(p.seg_ctr + ((tag + 1u) & 1u), 0u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     *gp(p.gen) = tag;
   }
 }

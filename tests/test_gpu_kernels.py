@@ -128,3 +128,60 @@ def test_heavily_flagged_tiles_match_the_dense_route(ctx, pk, oracle_lib):
     (c, nc), (e, ne) = both(ctx, pk, lambda: ctx.pulscan_search_ex(d, Z, C, 1.0, opts=low))
     assert nc == ne == na
     assert c.tobytes() == e.tobytes() == a.tobytes()
+
+
+def test_mixed_zmax_batch_matches_each_search(ctx, pk, oracle_lib):
+    # a batch mixing small and large zmax, whose ranges the streaming
+    # kernel's workgroups take in an order that depends on their speed: the
+    # candidates are those of the tiled kernel and of every spectrum searched
+    # alone
+    shapes = [(1 << 17, 8), (150001, 300), (1 << 17, 16), (90000, 300), (70001, 8)]
+    xs = [spectrum(oracle_lib, n, z, 1024, seed=90 + s, red=0.01) for s, (n, z) in enumerate(shapes)]
+    ds = [to_device(x) for x in xs]
+    zs = [z for _, z in shapes]
+    say("mixed zmax batch")
+    (a, na, ca), (b, nb, cb) = both(ctx, pk, lambda: ctx.pulscan_search_batched(ds, zs, 1024, 6.0))
+    assert na == nb > 0 and ca == cb == 1024
+    assert a.tobytes() == b.tobytes()
+    parts = []
+    for s, (d, z) in enumerate(zip(ds, zs)):
+        g, _ = ctx.pulscan_search_ex(d, z, 1024, 6.0)
+        g["spectrum"] = s
+        parts.append(g)
+    assert np.concatenate(parts).tobytes() == a.tobytes()
+
+
+def test_ranges_taken_in_turn_give_the_same_candidates(ctx, pk):
+    # a batch long enough (64 spectra of 2^20..2^23 bins, about 2.9e8) for
+    # the streaming kernel to cut it into several ranges per workgroup, which
+    # workgroups take from a counter in an order that varies between runs:
+    # the candidates stay those of the tiled kernel, of a second run, and of
+    # every spectrum searched alone
+    import torch
+    wls = synth.batched_workload(nspec=64, seed=11)
+
+    def tone_power(A, w, nt):
+        return float(ctx.pulscan_threshold_table(w, A, nt)[w - 1])
+
+    xs = [synth.make_spectrum_device(w, tone_power)[0] for w in wls]
+    zs = [w.zmax for w in wls]
+    torch.cuda.synchronize()
+    say(f"ranges taken in turn: {sum(w.nbins for w in wls)} bins")
+    ctx.pulscan_ctx_set_kernel(pk.PULSCAN_KERNEL_STREAM)
+    try:
+        a, na, _ = ctx.pulscan_search_batched(xs, zs, 1024, 6.0)
+        b, nb, _ = ctx.pulscan_search_batched(xs, zs, 1024, 6.0)
+        ctx.pulscan_ctx_set_kernel(pk.PULSCAN_KERNEL_TILED)
+        c, nc, _ = ctx.pulscan_search_batched(xs, zs, 1024, 6.0)
+    finally:
+        ctx.pulscan_ctx_set_kernel(pk.PULSCAN_KERNEL_AUTO)
+    assert na == nb == nc > 0
+    assert a.tobytes() == b.tobytes() == c.tobytes()
+    parts = []
+    for s, (d, z) in enumerate(zip(xs, zs)):
+        g, _ = ctx.pulscan_search_ex(d, z, 1024, 6.0)
+        g["spectrum"] = s
+        parts.append(g)
+    assert np.concatenate(parts).tobytes() == a.tobytes()
+    del xs
+    torch.cuda.empty_cache()
