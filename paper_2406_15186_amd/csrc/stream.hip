@@ -813,12 +813,26 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
   // the next launch.
   uint32_t *const seg_ctr = p.seg_ctr ? p.seg_ctr + (tag & 1u) : nullptr;
   for (uint32_t seg = wg; seg < nseg;) {
-    // (the divisor through an empty asm: the division's set-up is then made
-    // here, once per range, instead of held in registers across the loop)
+    // The range [g0, g1): with one range per workgroup, equal ones; with
+    // several, ranges that shrink along the launch (range i starts at
+    // units (i N + 3 (N^2 - (N - i)^2)) / 4N^2, N = nseg: the first about
+    // 1.75 times the mean, the last a quarter of it), so that the ranges
+    // taken last, which set how far apart the workgroups end, are short.
+    // (The divisor goes through an empty asm: the division's set-up is then
+    // made here, once per range, instead of held in registers across the
+    // loop.)
     uint32_t ns = nseg;
     asm volatile("" : "+s"(ns));
-    const uint64_t g0 = uniform64(units * seg / ns * p.align);
-    const uint64_t g1 = uniform64(units * (seg + 1) / ns * p.align);
+    uint64_t g0, g1;
+    if (ns == nwg) {
+      g0 = uniform64(units * seg / ns * p.align);
+      g1 = uniform64(units * (seg + 1) / ns * p.align);
+    } else {
+      const uint64_t N = ns, r0 = N - seg, r1 = r0 - 1;
+      g0 = uniform64(units * ((uint64_t)seg * N + 3 * (N * N - r0 * r0)) / (4 * N * N) * p.align);
+      g1 = uniform64(units * ((uint64_t)(seg + 1) * N + 3 * (N * N - r1 * r1)) / (4 * N * N) *
+                     p.align);
+    }
     uint32_t wg_count = 0;  // candidates staged so far in this range (uniform)
 
     // the series holding block g0
