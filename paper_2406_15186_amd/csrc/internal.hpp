@@ -141,13 +141,14 @@ hipError_t launch_bank(const Geometry &g, const BankParams &p, uint64_t grid, hi
 constexpr int kStreamWaves = 8;                       // waves per workgroup
 constexpr int kStreamThreads = 64 * kStreamWaves;
 constexpr int kStreamBatch = kStreamWaves;            // blocks normalised per batch
-// A long launch is cut into up to kStreamRounds ranges per workgroup, each
-// of at least kStreamRangeMin blocks; a workgroup that has finished a range
-// takes the next one not yet taken, so that workgroups slowed by their
-// series (zmax, flagged lanes) or by their CU take fewer, and all finish
-// within about one range of each other
+// A long launch is cut into up to kStreamRounds ranges per workgroup, of at
+// least kStreamRangeMin blocks on average (the last ones a quarter of the
+// mean); a workgroup that has finished a range takes the next one not yet
+// taken, so that workgroups slowed by their series (zmax, flagged lanes) or
+// by their CU take fewer, and all finish within about one range of each
+// other
 constexpr uint32_t kStreamRounds = 16;
-constexpr uint64_t kStreamRangeMin = 256;
+constexpr uint64_t kStreamRangeMin = 64;
 constexpr uint32_t kStreamSpin = 1u << 20;            // polls of a cross-workgroup word before giving up
 
 struct StreamGeometry {

@@ -866,8 +866,8 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
       const uint32_t lgs = (zc + B - 1) / B;       // halo blocks of this series
       // the previous range needs our first blocks; with several ranges per
       // workgroup the ranges' neighbours run at unrelated times, and each
-      // range normalises its halo blocks itself (lag blocks in a range of at
-      // least kStreamRangeMin)
+      // range normalises its halo blocks itself (lag blocks against ranges
+      // of kStreamRangeMin blocks on average)
       const bool publish = nseg == nwg && a > 0 && gc == g0;
       const bool consume = b < nbs;                // our last tile reaches into the next range
       const uint32_t zpub = min(lgs, b - a);
