@@ -630,7 +630,6 @@ int enqueue(pulscan_ctx *ctx, const std::vector<SpecIn> &specs, const RunArgs &a
     sp.single = descs[0];
     sp.nspec = nspec;
     sp.total_blocks = blocks;
-    sp.align = 1;
     sp.nwg = (uint32_t)nwg;
     sp.nseg = (uint32_t)nseg;
     sp.chunk = a.chunk;

@@ -168,7 +168,6 @@ struct StreamParams {
   SpecDesc single;         // the series when nspec == 1
   int nspec;
   uint64_t total_blocks;   // padded blocks of the whole launch
-  uint32_t align;          // blocks per alignment unit (range boundaries)
   uint32_t nwg;            // workgroups
   uint32_t nseg;           // ranges: workgroup w takes ranges w, w + nwg, ... (nseg >= nwg)
   uint32_t chunk;          // C

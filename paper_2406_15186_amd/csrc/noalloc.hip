@@ -206,7 +206,6 @@ extern "C" int pulscan_search_noalloc(const pulscan_complex *spectrum, size_t nb
   sp.single = d;
   sp.nspec = 1;
   sp.total_blocks = blocks;
-  sp.align = 1;
   sp.nwg = (uint32_t)nwg;
   sp.nseg = (uint32_t)nwg;  // one range per workgroup: the scratch holds nwg words
   sp.chunk = (uint32_t)chunk;

@@ -767,7 +767,17 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
   const SpecDesc *descs = p.descs;
   const int nspec = p.nspec;
   const uint32_t nwg = p.nwg, C = p.chunk, spin = p.spin, pool_cap = p.pool_cap;
+  // chunks tile the block (a power of two), so C is one: divisions by it are
+  // shifts (a division by a runtime value would keep its reciprocal live)
+  const uint32_t lgC = __builtin_ctz(C);
   const uint32_t RB = p.g.ring, lag = p.g.lag;
+  // x mod RB, with RB through an empty asm at each use: the division's set-up
+  // is then made there instead of its reciprocal held in a register
+  auto ring_mod = [&](uint32_t x) __attribute__((always_inline)) {
+    uint32_t rb = RB;
+    asm volatile("" : "+s"(rb));
+    return x % rb;
+  };
   StageEntry *const pool = p.pool;
   uint32_t *const pool_head = p.pool_head;
   unsigned long long *const halo = p.halo;
@@ -791,7 +801,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
 
   const uint32_t wg = blockIdx.x;
   const uint32_t tag = *gp(p.gen) + 1u;
-  const uint64_t units = p.total_blocks / p.align;
+  const uint64_t units = p.total_blocks;
   const uint32_t nseg = p.nseg;
   const bool search = PRUNE || p.mode == kModeSearch;
   constexpr bool prune = PRUNE;
@@ -824,14 +834,13 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     uint32_t ns = nseg;
     asm volatile("" : "+s"(ns));
     uint64_t g0, g1;
-    if (ns == nwg) {
-      g0 = uniform64(units * seg / ns * p.align);
-      g1 = uniform64(units * (seg + 1) / ns * p.align);
+    if (nseg == nwg) {  // (not ns: the compiler would then divide by nwg)
+      g0 = uniform64(units * seg / ns);
+      g1 = uniform64(units * (seg + 1) / ns);
     } else {
       const uint64_t N = ns, r0 = N - seg, r1 = r0 - 1;
-      g0 = uniform64(units * ((uint64_t)seg * N + 3 * (N * N - r0 * r0)) / (4 * N * N) * p.align);
-      g1 = uniform64(units * ((uint64_t)(seg + 1) * N + 3 * (N * N - r1 * r1)) / (4 * N * N) *
-                     p.align);
+      g0 = uniform64(units * ((uint64_t)seg * N + 3 * (N * N - r0 * r0)) / (4 * N * N));
+      g1 = uniform64(units * ((uint64_t)(seg + 1) * N + 3 * (N * N - r1 * r1)) / (4 * N * N));
     }
     uint32_t wg_count = 0;  // candidates staged so far in this range (uniform)
 
@@ -937,8 +946,8 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         const uint32_t tb0 = t0 * B;
         const uint32_t tbins = min((t1 - t0) * B, n - tb0);   // window starts
         const uint32_t nlane = (tbins + K - 1) / K;            // lanes with starts
-        const uint32_t gb = ((t0 - a) % RB) * GPB;             // ring position of the tile's group 0
-        const uint32_t nch = (tbins + C - 1) / C, chunk0 = tb0 / C;
+        const uint32_t gb = ring_mod(t0 - a) * GPB;             // ring position of the tile's group 0
+        const uint32_t nch = (tbins + C - 1) >> lgC, chunk0 = tb0 >> lgC;
         const uint32_t nsl = nch * zmax;
         const uint32_t nbw = (zmax + K - 1) / K;               // width blocks
         // tile tc counts its flagged lanes in items[tc % 3].  After its first
@@ -984,7 +993,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
             // the lane index taken afresh per unit: its masks and addresses are
             // rebuilt here rather than held across the workgroup's loops
             exact_unit<K>(R, R.wrap(gb + L), fb, pass, Tl, zmax, nblk,
-                          slots + (size_t)((L * K) / C) * zmax, tb0 + L * K, xs, ftid() & 63);
+                          slots + (size_t)((L * K) >> lgC) * zmax, tb0 + L * K, xs, ftid() & 63);
           }
         } else {
           // units (lane, width block, start group): lane-major pairs, every 64
@@ -1003,7 +1012,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
             if (ok && bw >= (it & 0xFFFu)) {
               const uint32_t L = it >> 12;
               const uint32_t q = R.wrap(gb + L);
-              unsigned long long *row = slots + (size_t)((L * K) / C) * zmax;
+              unsigned long long *row = slots + (size_t)((L * K) >> lgC) * zmax;
               if constexpr (NH == 1) {
                 eval_unit<K, 0>(R, q, bw, Tl, zmax, row, tb0 + L * K);
               } else {
@@ -1091,7 +1100,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         if (k < b) {
           NormOut o = no;
           o.pub = (publish && k - a < zpub) ? pw + 4 * (k - a) : nullptr;
-          normalise<K, EPL, FP>(d, k, r, false, BlockStats{}, B, R, (k - a) % RB, o, lane);
+          normalise<K, EPL, FP>(d, k, r, false, BlockStats{}, B, R, ring_mod(k - a), o, lane);
         }
         __syncthreads();
         const uint32_t ready = j + 1 == nbat ? (b > lgs ? b - lgs : 0u)
@@ -1126,7 +1135,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
         const uint32_t k = b + wave;
         if (wave < lgs) {
           const uint32_t limit = min(B, (zc - wave * B + 63) / 64 * 64);
-          const uint32_t slot = (k - a) % RB;
+          const uint32_t slot = ring_mod(k - a);
           if (k >= nbs) {
             // no spectrum behind these bins
             fill_past_end<K, EPL>(R, slot, limit, lane);
