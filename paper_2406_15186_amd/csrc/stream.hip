@@ -3,20 +3,23 @@
 // every width, the per-chunk maxima with the threshold test and the staging
 // of the candidates, reading every bin of a range from HBM once.
 //
-//  * Ranges.  A launch is cut into nseg equal ranges.  Workgroup w takes
-//    range w, then the next range that no workgroup has taken (a counter in
-//    global memory), so that the workgroups a batch's series slow down (a
-//    larger zmax, a tone's flagged lanes, a busier CU) take fewer ranges and
-//    every workgroup ends within about one range of the others.  Single
-//    spectra use one range per workgroup.
+//  * Ranges.  A launch is cut into nseg ranges.  Workgroup w takes range w,
+//    then the next range that no workgroup has taken (a counter in global
+//    memory), so that the workgroups a batch's series slow down (a larger
+//    zmax, a tone's flagged lanes, a busier CU) take fewer ranges and every
+//    workgroup ends within about one range of the others; the ranges shrink
+//    along the launch, so that the last ones taken are short.  Launches
+//    below about 67 M bins use one equal range per workgroup.
 //  * Streaming.  A workgroup's range (a run of blocks of one or more series)
 //    is taken a batch of kStreamBatch blocks at a time, one block per wave.
 //    The next batch's loads are in flight (in registers) while the current
 //    one is normalised and searched, and the one after is requested as soon
-//    as a batch has been normalised (batch 1 only once batch 0 is in).  Every issue is the same number of unconditional loads, so
-//    that the compiler's wait counts never hold one batch for the next.  Normalised power goes to an LDS ring of blocks; a tile of
-//    blocks is searched once the ring holds every bin its windows reach
-//    (zmax - 1 bins past its end, `lag` blocks).
+//    as a batch has been normalised (batch 1 only once batch 0 is in).
+//    Every issue is the same number of unconditional loads, so that the
+//    compiler's wait counts never hold one batch for the next.  Normalised
+//    power goes to an LDS ring of blocks; a tile of blocks is searched once
+//    the ring holds every bin its windows reach (zmax - 1 bins past its end,
+//    `lag` blocks).
 //  * Halo.  The windows of a range's last tile reach into the next range,
 //    which another workgroup normalises.  That workgroup publishes the four
 //    statistics of its first `lag` blocks as soon as it has them; the
@@ -815,7 +818,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     sh.items[2] = 0u;
   }
 
-  // the ranges of this workgroup, of nseg equal ones: range w first, then
+  // the ranges of this workgroup, of the launch's nseg: range w first, then
   // the next one not yet taken (from the launch's counter) or, without a
   // counter, w + nwg, w + 2 nwg, ...  The counters alternate between
   // launches: launch tag t takes from seg_ctr[t & 1], whose last increments
@@ -830,7 +833,7 @@ __global__ __launch_bounds__(kStreamThreads, 4) void stream_kernel(StreamParams 
     // taken last, which set how far apart the workgroups end, are short.
     // (The divisor goes through an empty asm: the division's set-up is then
     // made here, once per range, instead of held in registers across the
-    // loop.)
+    // loop.  units 4N^2 stays below 2^64 for launches below 10^13 bins.)
     uint32_t ns = nseg;
     asm volatile("" : "+s"(ns));
     uint64_t g0, g1;
